@@ -1,0 +1,161 @@
+/*
+ * truth.c -- independent long-double references for the exponential of the
+ * drag matrix (TEST INFRASTRUCTURE ONLY; see oracle.c).
+ *
+ * These do not use scaling and squaring.  They pin the oracle to results
+ * that follow from the mathematics alone:
+ *
+ * truth_expm_eigen -- exp(dt K) from the eigen-decomposition of the
+ *   symmetrised matrix.  With w = (1, sqrt(e_1), .., sqrt(e_N)),
+ *   S = diag(w) A diag(w)^-1 is a symmetric arrowhead matrix
+ *   (S00 = -sum e_i a_i, S0i = a_i sqrt(e_i), Sii = -a_i).  Its eigenvalues
+ *   are 0 (eigenvector w) and the N roots of the secular equation
+ *   1 + sum_i e_i a_i / (lambda + a_i) = 0, one between each pair of
+ *   consecutive poles -a_(j+1) < lambda < -a_(j) and one below -a_max; the
+ *   eigenvector of a root is (1, a_i sqrt(e_i) / (lambda + a_i)).  Each root
+ *   is bracketed by bisection with the origin moved to the nearer pole, so
+ *   lambda + a_i keeps its relative accuracy.  Requires e_i > 0 and distinct
+ *   a_i > 0 (returns -1 otherwise).  The exact result is
+ *   E_jk = (w_k / w_j) sum_l x_jl x_kl exp(lambda_l).
+ *
+ * truth_expm_taylor -- the plain power series sum_{i<=terms} A^i / i! in long
+ *   double, meaningful for ||A||_1 <= 7 (the largest term then stays below
+ *   e^7 and the long-double cancellation error below 1e-16).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+typedef long double ld_t;
+
+/* f(mu) with lambda = -a_p + mu, written with the shifted differences
+ * lambda + a_i = mu + (a_i - a_p). */
+static ld_t secular(int N, const ld_t *a, const ld_t *e, int p, ld_t mu)
+{
+    ld_t f = 1.0L;
+    for (int i = 0; i < N; ++i) {
+        ld_t den = (i == p) ? mu : mu + (a[i] - a[p]);
+        f += e[i] * a[i] / den;
+    }
+    return f;
+}
+
+/* Root of the secular equation in the open interval (lo, hi) of lambda, where
+ * f(lo+) = +inf and f(hi-) = -inf (f decreases between poles).  p_lo / p_hi
+ * are the pole indices bounding the interval (-1: none).  Returns the pole
+ * index p used as origin and mu = lambda + a_p. */
+static void secular_root(int N, const ld_t *a, const ld_t *e, ld_t lo, ld_t hi,
+                         int p_lo, int p_hi, int *p_out, ld_t *mu_out)
+{
+    ld_t mid = 0.5L * (lo + hi);
+    int p;
+    if (p_hi < 0) {
+        p = p_lo;
+    } else if (p_lo < 0) {
+        p = p_hi;
+    } else {
+        /* f decreasing: f(mid) > 0 means the root is right of mid (near hi) */
+        ld_t fm = secular(N, a, e, p_hi, mid + a[p_hi]);
+        p = (fm > 0) ? p_hi : p_lo;
+    }
+    ld_t mlo = lo + a[p], mhi = hi + a[p];
+    if (p == p_lo) mlo = 0.0L; /* exact pole on the left */
+    if (p == p_hi) mhi = 0.0L; /* exact pole on the right */
+    for (int it = 0; it < 400; ++it) {
+        ld_t mm = 0.5L * (mlo + mhi);
+        if (mm == mlo || mm == mhi) break;
+        ld_t f = secular(N, a, e, p, mm);
+        if (f > 0) mlo = mm;
+        else mhi = mm;
+    }
+    *p_out = p;
+    *mu_out = 0.5L * (mlo + mhi);
+}
+
+int truth_expm_eigen(int N, double dt, double rho_g, const double *rho_d,
+                     const double *t_stop, double *E)
+{
+    const int n = N + 1;
+    if (N < 1 || n > ORC_NMAX) return -1;
+    ld_t a[ORC_NMAX], e[ORC_NMAX], w[ORC_NMAX];
+    int ord[ORC_NMAX];
+    for (int i = 0; i < N; ++i) {
+        a[i] = (ld_t)dt / (ld_t)t_stop[i];
+        e[i] = (ld_t)rho_d[i] / (ld_t)rho_g;
+        if (!(a[i] > 0) || !(e[i] > 0) || !isfinite((double)a[i])) return -1;
+        ord[i] = i;
+    }
+    /* species sorted by a ascending (insertion sort) */
+    for (int i = 1; i < N; ++i) {
+        int t = ord[i], j = i - 1;
+        while (j >= 0 && a[ord[j]] > a[t]) { ord[j + 1] = ord[j]; --j; }
+        ord[j + 1] = t;
+    }
+    for (int i = 1; i < N; ++i)
+        if (!(a[ord[i]] > a[ord[i - 1]])) return -1;
+
+    w[0] = 1.0L;
+    for (int i = 0; i < N; ++i) w[i + 1] = sqrtl(e[i]);
+
+    /* eigenvectors of S as columns of X (n x n), eigenvalues lam */
+    ld_t X[ORC_NMAX][ORC_NMAX], lam[ORC_NMAX];
+    /* the conserved mode: lambda = 0, x = w */
+    lam[0] = 0.0L;
+    for (int j = 0; j < n; ++j) X[j][0] = w[j];
+
+    ld_t sum_ea = 0.0L;
+    for (int i = 0; i < N; ++i) sum_ea += e[i] * a[i];
+    for (int r = 0; r < N; ++r) {
+        /* interval between -a_(r+1) (left) and -a_(r) (right); the last one
+         * is (-a_max - sum e a, -a_max) */
+        int p_hi = ord[r];
+        int p_lo = (r + 1 < N) ? ord[r + 1] : -1;
+        ld_t hi = -a[p_hi];
+        ld_t lo = (p_lo >= 0) ? -a[p_lo] : -a[p_hi] - sum_ea;
+        int p;
+        ld_t mu;
+        secular_root(N, a, e, lo, hi, p_lo, p_hi, &p, &mu);
+        lam[r + 1] = -a[p] + mu;
+        X[0][r + 1] = 1.0L;
+        for (int i = 0; i < N; ++i) {
+            ld_t den = (i == p) ? mu : mu + (a[i] - a[p]);
+            X[i + 1][r + 1] = a[i] * sqrtl(e[i]) / den;
+        }
+    }
+    for (int l = 0; l < n; ++l) {
+        ld_t nrm2 = 0.0L;
+        for (int j = 0; j < n; ++j) nrm2 += X[j][l] * X[j][l];
+        ld_t inv = 1.0L / sqrtl(nrm2);
+        for (int j = 0; j < n; ++j) X[j][l] *= inv;
+    }
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) {
+            ld_t acc = 0.0L;
+            for (int l = 0; l < n; ++l) acc += X[j][l] * X[k][l] * expl(lam[l]);
+            E[j * n + k] = (double)(acc * w[k] / w[j]);
+        }
+    return 0;
+}
+
+int truth_expm_taylor(int n, const double *A, int terms, double *E)
+{
+    if (n < 1 || n > ORC_NMAX) return -1;
+    ld_t T[ORC_NMAX * ORC_NMAX], U[ORC_NMAX * ORC_NMAX], S[ORC_NMAX * ORC_NMAX];
+    for (int i = 0; i < n * n; ++i) { T[i] = 0.0L; S[i] = 0.0L; }
+    for (int i = 0; i < n; ++i) { T[i * n + i] = 1.0L; S[i * n + i] = 1.0L; }
+    for (int it = 1; it <= terms; ++it) {
+        /* T <- T A / it */
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                ld_t acc = 0.0L;
+                for (int k = 0; k < n; ++k) acc += T[i * n + k] * (ld_t)A[k * n + j];
+                U[i * n + j] = acc / (ld_t)it;
+            }
+        memcpy(T, U, sizeof(ld_t) * n * n);
+        for (int i = 0; i < n * n; ++i) S[i] += T[i];
+    }
+    for (int i = 0; i < n * n; ++i) E[i] = (double)S[i];
+    return 0;
+}
