@@ -1,0 +1,201 @@
+/*
+ * dragexp.h -- C ABI of the MI355X (gfx950) drag-update library.
+ *
+ * For every cell of a grid the library advances the gas and N dust velocities
+ * through one drag step,
+ *
+ *     v(t + dt) = exp(dt K) v,
+ *
+ * the exact solution of the linear drag ODE of Sewanou, Laibe and Commercon
+ * (arXiv:2509.25347), Sect. 2.2, eqs. DragEq-jacobian and ExacSolEqu, written
+ * for velocities: dv_i/dt = -(v_i - v_g)/t_i for dust species i and
+ * dv_g/dt = sum_i (rho_i/rho_g)(v_i - v_g)/t_i for the gas.  The exponential
+ * is the Taylor scaling-and-squaring approximant of Sect. 2.3 and Appendix B
+ * (Alg. 1 option `option`, at most `k_max` products in the polynomial stage),
+ * accurate to the IEEE double unit round-off u = 2^-53 in the backward sense
+ * (eqs. B1-B8).  All arithmetic is FP64.
+ *
+ * Memory layout (structure of arrays, the cell index fastest, leading
+ * dimension ld >= n_cells, all in elements):
+ *     rho_g  [C]                 gas density                  rho_g[c]
+ *     rho_d  [N][ld]             dust densities               rho_d[i*ld + c]
+ *     t_stop [N][ld]             stopping times T_s,i         t_stop[i*ld + c]
+ *     v      [D][N+1][ld]        velocities, row 0 = gas      v[(d*(N+1) + j)*ld + c]
+ * with N = n_species in [1, 16] and D = n_dim in [1, 3]; the D components
+ * share one matrix K.
+ *
+ * Ownership and synchronisation: every array pointer is a device pointer
+ * owned by the caller.  Calls only enqueue work on `stream` (a hipStream_t;
+ * NULL is the null stream); they never allocate device memory, never
+ * synchronise, and return before the work is done -- except
+ * drag_get_status, which synchronises `stream`.
+ *
+ * Errors: a negative return value is an argument error found on the host
+ * before anything was enqueued.  Invalid per-cell data (rho_g not finite or
+ * <= 0; rho_d not finite or < 0; t_stop NaN or <= 0; a velocity not finite;
+ * ||dt K||_1 overflowing) is not an argument error: that cell's outputs are
+ * NaN and the matching DRAG_CELL_* bit is ORed into a per-device sticky
+ * status word (drag_get_status / drag_clear_status).  t_stop = +inf is valid
+ * (a decoupled species); rho_d = 0 is valid (no back-reaction).
+ */
+#ifndef DRAGEXP_H
+#define DRAGEXP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+#define DRAG_OK                 0
+#define DRAG_ERR_NULL_DESC     -1  /* desc pointer is NULL */
+#define DRAG_ERR_N_CELLS       -2  /* n_cells < 0 */
+#define DRAG_ERR_N_SPECIES     -3  /* n_species outside [1, 16] */
+#define DRAG_ERR_N_DIM         -4  /* n_dim outside [1, 3] */
+#define DRAG_ERR_LD            -5  /* ld < n_cells, or ld too large for 64-bit offsets */
+#define DRAG_ERR_DT            -6  /* dt NaN, infinite or < 0 */
+#define DRAG_ERR_K_MAX         -7  /* k_max outside [1, 9] */
+#define DRAG_ERR_OPTION        -8  /* option not 0, 1 or 2 */
+#define DRAG_ERR_NULL_POINTER  -9  /* a required array pointer is NULL (n_cells > 0) */
+#define DRAG_ERR_ALIAS        -10  /* an output overlaps an input it may not alias */
+#define DRAG_ERR_PLAN         -11  /* invalid batched plan or block table */
+#define DRAG_ERR_HIP          -20  /* the HIP runtime reported an error */
+
+/* per-cell bits of the sticky device status word */
+#define DRAG_CELL_BAD_DENSITY       1
+#define DRAG_CELL_BAD_STOPPING_TIME 2
+#define DRAG_CELL_BAD_VELOCITY      4
+#define DRAG_CELL_BAD_NORM          8
+
+/* an opaque hipStream_t */
+typedef void *drag_stream_t;
+
+typedef struct drag_desc {
+    int64_t n_cells;   /* C >= 0; C = 0 is a no-op */
+    int32_t n_species; /* N in [1, 16] */
+    int32_t n_dim;     /* D in [1, 3] */
+    int64_t ld;        /* leading dimension of every [.][ld] array, >= C */
+    double dt;         /* finite, >= 0; dt = 0 returns v unchanged, bit for bit */
+    int32_t k_max;     /* K of Alg. 1, 1..9 (9: m up to 30, Table B.1) */
+    int32_t option;    /* Alg. 1 option: 0 standard, 1, 2 (fewest products) */
+} drag_desc;
+
+/* Fill `d` with the defaults: k_max = 9, option = 2, ld = n_cells. */
+void drag_desc_init(drag_desc *d, int64_t n_cells, int32_t n_species,
+                    int32_t n_dim, double dt);
+
+/*
+ * drag_build -- the per-cell quantities of the method (Sect. 2.2 eqs.
+ * DragEqVar2-3; Appendix B, Alg. 1):
+ *   a_out[i*ld + c] = dt / t_i           (IEEE-rounded division)
+ *   e_out[i*ld + c] = rho_i / rho_g
+ *   norm_out[c]     = ||dt K||_1: the largest column sum of |dt K| in the
+ *                     velocity form, the gas column summed gas row first and
+ *                     then the species in ascending order, without fused
+ *                     multiply-adds (so it is reproducible bit for bit)
+ *   k_out, m_out, s_out [c]: (k*, m*, s*) of Alg. 1 for that norm.
+ * Any output pointer may be NULL (not computed).  Bad cells get NaN
+ * a/e/norm and k = m = s = 0.
+ */
+int drag_build(const drag_desc *desc, const double *rho_g, const double *rho_d,
+               const double *t_stop, double *a_out, double *e_out,
+               double *norm_out, int32_t *k_out, int32_t *m_out,
+               int32_t *s_out, drag_stream_t stream);
+
+/*
+ * drag_expm_apply -- v_out = exp(dt K) v_in for every cell (Sect. 2.2 eq.
+ * ExacSolEqu; Sect. 2.3; Appendix B Alg. 1 and the Taylor evaluation).
+ * v_out may be the same pointer as v_in (in place); any other overlap of
+ * v_out with an input is DRAG_ERR_ALIAS.
+ */
+int drag_expm_apply(const drag_desc *desc, const double *rho_g,
+                    const double *rho_d, const double *t_stop,
+                    const double *v_in, double *v_out, drag_stream_t stream);
+
+/*
+ * drag_expm_apply_backward -- the adjoint of drag_expm_apply for the loss
+ * L = sum_{d,j,c} grad_v_out[d][j][c] * v_out[d][j][c] (the chain rule of a
+ * training step: grad_v_out = dL/dv_out).  The exponential is differentiated
+ * with (k*, m*, s*) held fixed; nothing is stored between forward and
+ * backward: the Taylor stage and the squaring chain are recomputed.
+ *   v_out       [D][N+1][ld] or NULL: the forward result (fused forward)
+ *   grad_v_in   [D][N+1][ld] or NULL: dL/dv_in
+ *   grad_log_t  [N][ld] or NULL:      dL/d(log t_i)
+ *   grad_rho_d  [N][ld] or NULL:      dL/d rho_i
+ *   grad_rho_g  [C] or NULL:          dL/d rho_g
+ * No output may overlap an input or another output.
+ */
+int drag_expm_apply_backward(const drag_desc *desc, const double *rho_g,
+                             const double *rho_d, const double *t_stop,
+                             const double *v_in, const double *grad_v_out,
+                             double *v_out, double *grad_v_in,
+                             double *grad_log_t, double *grad_rho_d,
+                             double *grad_rho_g, drag_stream_t stream);
+
+/* ---- batched blocks with uneven species counts -------------------------- */
+/*
+ * A batch is n_blocks blocks of block_cells cells (AMR-style blocks), block b
+ * with its own species count N_b in [1, 16].  Block b's fields are one
+ * contiguous slab of the caller's `fields` buffer starting at element
+ * field_offset[b] (as returned by drag_plan_offsets):
+ *     rho_g [block_cells] | rho_d [N_b][block_cells] | t_stop [N_b][block_cells]
+ * and its velocities one slab of `v` starting at v_offset[b]:
+ *     v [D][N_b + 1][block_cells].
+ * The plan (created once, on the host and the current device) holds the
+ * device block table, the launch configuration chosen per N by the
+ * autotuner, and an instantiated hipGraph of the persistent launch.
+ */
+typedef struct drag_plan drag_plan;
+
+typedef struct drag_batch_desc {
+    int32_t n_blocks;         /* >= 1 */
+    int32_t block_cells;      /* cells per block, >= 1 */
+    int32_t n_dim;            /* D in [1, 3] */
+    int32_t k_max;            /* 1..9 */
+    int32_t option;           /* 0, 1, 2 */
+    double dt;                /* finite, >= 0 */
+    const int32_t *n_species; /* host array [n_blocks], each in [1, 16] */
+} drag_batch_desc;
+
+int drag_plan_batched(const drag_batch_desc *desc, drag_plan **out);
+/* Element offsets of every block's slabs and the total buffer sizes. */
+int drag_plan_offsets(const drag_plan *plan, int64_t *field_offset,
+                      int64_t *v_offset, int64_t *fields_total,
+                      int64_t *v_total);
+/* v_out may equal v_in; otherwise no overlap.  Replays the plan's graph
+ * when the pointers match the captured ones, else updates it first. */
+int drag_expm_apply_batched(drag_plan *plan, const double *fields,
+                            const double *v_in, double *v_out,
+                            drag_stream_t stream);
+int drag_plan_destroy(drag_plan *plan);
+
+/* ---- status and introspection -------------------------------------------- */
+/* Synchronise `stream`, then read the current device's sticky status word. */
+int drag_get_status(drag_stream_t stream, int32_t *host_status);
+/* Enqueue a reset of the current device's status word on `stream`. */
+int drag_clear_status(drag_stream_t stream);
+const char *drag_status_string(int code);
+
+/* Row k (1..9) of the library's copy of Table B.1 (Appendix B). */
+int drag_table_row(int k, int32_t *m, int32_t *q, int32_t *r, double *theta);
+/* (k*, m*, s*) of Alg. 1 for a finite norm, computed on the host by the same
+ * code the kernels run. */
+int drag_select(double norm, int32_t k_max, int32_t option, int32_t *k,
+                int32_t *m, int32_t *s);
+
+/* ---- launch tuning ------------------------------------------------------------ */
+/* The per-N mapping used by drag_expm_apply and the batched plan:
+ * DRAG_MAP_LANE (one cell per lane, VALU) or DRAG_MAP_WAVE (one cell per
+ * 64-lane wavefront, FP64 MFMA).  DRAG_MAP_AUTO restores the tuned default. */
+#define DRAG_MAP_AUTO 0
+#define DRAG_MAP_LANE 1
+#define DRAG_MAP_WAVE 2
+int drag_set_mapping(int32_t n_species, int32_t mapping);
+int drag_get_mapping(int32_t n_species, int32_t *mapping);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DRAGEXP_H */

@@ -212,6 +212,7 @@ int orc_build(int N, double dt, double rho_g, const double *rho_d,
     if (bad) { *nrm = NAN; return bad; }
 
     double s = 0.0;
+    int overflow = 0;
     for (int i = 1; i <= N; ++i) {
         a[i - 1] = dt / t_stop[i - 1];        /* t = +inf gives a = 0 */
         e[i - 1] = rho_d[i - 1] / rho_g;
@@ -220,6 +221,7 @@ int orc_build(int N, double dt, double rho_g, const double *rho_d,
         A[i * n + 0] = a[i - 1];              /* dust rows: drag toward gas */
         A[i * n + i] = -a[i - 1];
         s += p;
+        if (!isfinite(a[i - 1]) || !isfinite(p)) overflow = 1;
     }
     A[0] = -s;
 
@@ -231,7 +233,8 @@ int orc_build(int N, double dt, double rho_g, const double *rho_d,
         if (c > best) best = c;
     }
     *nrm = best;
-    if (!isfinite(best)) return ORC_BAD_NORM;
+    /* an entry of dt K that overflowed (0 * inf included) makes the cell bad */
+    if (overflow || !isfinite(best)) { *nrm = NAN; return ORC_BAD_NORM; }
     return 0;
 }
 

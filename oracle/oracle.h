@@ -15,7 +15,7 @@
 #define ORC_BAD_DENSITY       1 /* rho_g not finite or <= 0, rho_d not finite or < 0 */
 #define ORC_BAD_STOPPING_TIME 2 /* t_i NaN or <= 0 (t_i = +inf is valid: a_i = 0) */
 #define ORC_BAD_VELOCITY      4 /* a velocity (or loss weight) not finite */
-#define ORC_BAD_NORM          8 /* ||dt K||_1 overflowed */
+#define ORC_BAD_NORM          8 /* an entry or the 1-norm of dt K overflowed */
 
 int orc_table_row(int k, int *m, int *q, int *r, double *theta);
 double orc_taylor_coef(int i);

@@ -1,0 +1,338 @@
+// dragexp.hip -- kernels and C ABI of the MI355X drag-update library.
+//
+// v(t+dt) = exp(dt K) v per cell, Taylor scaling and squaring (Sewanou,
+// Laibe and Commercon, arXiv:2509.25347, Sect. 2.3 and Appendix B).  The ABI
+// is declared and documented in include/dragexp.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/dragexp.h"
+#include "common.hpp"
+#include "lane.hpp"
+#include "wave.hpp"
+
+namespace dragexp {
+
+constexpr int kLaneMaxN = 8;
+
+// ---- drag_build -------------------------------------------------------------
+struct BuildArgs {
+  const double* rho_g;
+  const double* rho_d;
+  const double* t_stop;
+  double* a_out;
+  double* e_out;
+  double* norm_out;
+  int32_t* k_out;
+  int32_t* m_out;
+  int32_t* s_out;
+  int64_t n_cells, ld;
+  double dt;
+  int n_species, k_max, option;
+};
+
+__global__ void __launch_bounds__(256) k_build(BuildArgs B, int xcd_blocks) {
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int64_t c = logical * 256 + threadIdx.x;
+  if (c >= B.n_cells) return;
+  const int N = B.n_species;
+  const int64_t ld = B.ld;
+  const double rg = B.rho_g[c];
+  unsigned bad = gas_bad(rg);
+  double s = 0.0;
+  bool finite = true;
+  for (int i = 0; i < N; ++i) {
+    const double t = B.t_stop[i * ld + c], r = B.rho_d[i * ld + c];
+    bad |= species_bad(t, r);
+    const Species sp = species_coeffs(B.dt, t, r, rg);
+    s = s + sp.p;
+    finite = finite && isfinite(sp.a) && isfinite(sp.p);
+  }
+  double nrm = s;
+  for (int i = 0; i < N; ++i) {
+    const Species sp = species_coeffs(B.dt, B.t_stop[i * ld + c], B.rho_d[i * ld + c], rg);
+    nrm = nrm + sp.a;
+  }
+  for (int i = 0; i < N; ++i) {
+    const Species sp = species_coeffs(B.dt, B.t_stop[i * ld + c], B.rho_d[i * ld + c], rg);
+    nrm = fmax(nrm, sp.p + sp.a);
+  }
+  if (!bad && !(finite && isfinite(nrm))) bad |= kBadNorm;
+  const double qnan = __builtin_nan("");
+  for (int i = 0; i < N; ++i) {
+    const Species sp = species_coeffs(B.dt, B.t_stop[i * ld + c], B.rho_d[i * ld + c], rg);
+    if (B.a_out) B.a_out[i * ld + c] = bad ? qnan : sp.a;
+    if (B.e_out) B.e_out[i * ld + c] = bad ? qnan : sp.e;
+  }
+  const Kms km = bad ? Kms{0, 0, 0} : select_kms(nrm, B.k_max, B.option);
+  if (B.norm_out) B.norm_out[c] = bad ? qnan : nrm;
+  if (B.k_out) B.k_out[c] = km.k;
+  if (B.m_out) B.m_out[c] = km.m;
+  if (B.s_out) B.s_out[c] = km.s;
+  if (bad) atomicOr(&g_status_word, bad);
+}
+
+__global__ void k_clear_status() { g_status_word = 0u; }
+
+// ---- launch helpers ------------------------------------------------------------
+struct Grid {
+  unsigned blocks;  // multiple of 8
+  int xcd_blocks;   // blocks / 8
+};
+
+static Grid grid_for(int64_t n_units) {
+  int64_t b = (n_units + 7) / 8 * 8;
+  if (b < 8) b = 8;
+  return Grid{(unsigned)b, (int)(b / 8)};
+}
+
+static int hip_status(hipError_t e) { return e == hipSuccess ? DRAG_OK : DRAG_ERR_HIP; }
+
+template <int N>
+static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
+  const Grid gr = grid_for((A.n_cells + 255) / 256);
+  hipLaunchKernelGGL(k_forward_lane<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
+template <int N>
+static int launch_forward_wave(const CellArgs& A, hipStream_t st) {
+  const Grid gr = grid_for((A.n_cells + 3) / 4);
+  hipLaunchKernelGGL(k_forward_wave<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
+using FwdFn = int (*)(const CellArgs&, hipStream_t);
+
+static FwdFn wave_fwd(int N) {
+  static const FwdFn tab[16] = {
+      launch_forward_wave<1>,  launch_forward_wave<2>,  launch_forward_wave<3>,
+      launch_forward_wave<4>,  launch_forward_wave<5>,  launch_forward_wave<6>,
+      launch_forward_wave<7>,  launch_forward_wave<8>,  launch_forward_wave<9>,
+      launch_forward_wave<10>, launch_forward_wave<11>, launch_forward_wave<12>,
+      launch_forward_wave<13>, launch_forward_wave<14>, launch_forward_wave<15>,
+      launch_forward_wave<16>};
+  return tab[N - 1];
+}
+
+static FwdFn lane_fwd(int N) {
+  static const FwdFn tab[kLaneMaxN] = {
+      launch_forward_lane<1>, launch_forward_lane<2>, launch_forward_lane<3>,
+      launch_forward_lane<4>, launch_forward_lane<5>, launch_forward_lane<6>,
+      launch_forward_lane<7>, launch_forward_lane<8>};
+  return tab[N - 1];
+}
+
+// Tuned default mapping per N (index N - 1).  Overridable with
+// drag_set_mapping.
+static int g_default_map[16] = {
+    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
+    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
+    DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
+    DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
+static int g_map_override[16] = {0};
+
+static int mapping_for(int N) {
+  const int o = g_map_override[N - 1];
+  int m = o ? o : g_default_map[N - 1];
+  if (m == DRAG_MAP_LANE && N > kLaneMaxN) m = DRAG_MAP_WAVE;
+  return m;
+}
+
+// ---- argument checks -------------------------------------------------------------
+static int check_desc(const drag_desc* d) {
+  if (!d) return DRAG_ERR_NULL_DESC;
+  if (d->n_cells < 0) return DRAG_ERR_N_CELLS;
+  if (d->n_species < 1 || d->n_species > kMaxSpecies) return DRAG_ERR_N_SPECIES;
+  if (d->n_dim < 1 || d->n_dim > 3) return DRAG_ERR_N_DIM;
+  if (d->ld < d->n_cells || d->ld < 1) return DRAG_ERR_LD;
+  // every index (row * ld + c) must fit in int64 with room to spare
+  if (d->ld > (INT64_MAX / 64)) return DRAG_ERR_LD;
+  if (!(d->dt >= 0.0) || !isfinite(d->dt)) return DRAG_ERR_DT;
+  if (d->k_max < 1 || d->k_max > 9) return DRAG_ERR_K_MAX;
+  if (d->option < 0 || d->option > 2) return DRAG_ERR_OPTION;
+  return DRAG_OK;
+}
+
+// [first, last) byte ranges of the arrays, for overlap checks
+struct Range {
+  uintptr_t lo, hi;
+};
+
+static Range span(const void* p, int64_t rows, int64_t ld, int64_t n_cells) {
+  if (!p || n_cells == 0) return Range{0, 0};
+  const uintptr_t lo = (uintptr_t)p;
+  const uintptr_t hi = lo + (uintptr_t)(((rows - 1) * ld + n_cells) * (int64_t)sizeof(double));
+  return Range{lo, hi};
+}
+
+static bool overlap(Range a, Range b) {
+  if (a.lo == a.hi || b.lo == b.hi) return false;
+  return a.lo < b.hi && b.lo < a.hi;
+}
+
+}  // namespace dragexp
+
+using namespace dragexp;
+
+extern "C" {
+
+void drag_desc_init(drag_desc* d, int64_t n_cells, int32_t n_species, int32_t n_dim,
+                    double dt) {
+  if (!d) return;
+  d->n_cells = n_cells;
+  d->n_species = n_species;
+  d->n_dim = n_dim;
+  d->ld = n_cells;
+  d->dt = dt;
+  d->k_max = 9;
+  d->option = 2;
+}
+
+int drag_build(const drag_desc* d, const double* rho_g, const double* rho_d,
+               const double* t_stop, double* a_out, double* e_out, double* norm_out,
+               int32_t* k_out, int32_t* m_out, int32_t* s_out, drag_stream_t stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (d->n_cells == 0) return DRAG_OK;
+  if (!rho_g || !rho_d || !t_stop) return DRAG_ERR_NULL_POINTER;
+  const int64_t C = d->n_cells, ld = d->ld, N = d->n_species;
+  const Range in[3] = {span(rho_g, 1, ld, C), span(rho_d, N, ld, C), span(t_stop, N, ld, C)};
+  const Range out[6] = {span(a_out, N, ld, C), span(e_out, N, ld, C), span(norm_out, 1, ld, C),
+                        Range{(uintptr_t)k_out, k_out ? (uintptr_t)(k_out + C) : 0},
+                        Range{(uintptr_t)m_out, m_out ? (uintptr_t)(m_out + C) : 0},
+                        Range{(uintptr_t)s_out, s_out ? (uintptr_t)(s_out + C) : 0}};
+  for (const Range& o : out) {
+    for (const Range& i : in)
+      if (overlap(o, i)) return DRAG_ERR_ALIAS;
+  }
+  for (int x = 0; x < 6; ++x)
+    for (int y = x + 1; y < 6; ++y)
+      if (overlap(out[x], out[y])) return DRAG_ERR_ALIAS;
+  BuildArgs B{rho_g, rho_d, t_stop, a_out, e_out, norm_out, k_out, m_out, s_out,
+              C,     ld,    d->dt,  (int)N, d->k_max, d->option};
+  const Grid gr = grid_for((C + 255) / 256);
+  hipLaunchKernelGGL(k_build, dim3(gr.blocks), dim3(256), 0, (hipStream_t)stream, B,
+                     gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
+int drag_expm_apply(const drag_desc* d, const double* rho_g, const double* rho_d,
+                    const double* t_stop, const double* v_in, double* v_out,
+                    drag_stream_t stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (d->n_cells == 0) return DRAG_OK;
+  if (!rho_g || !rho_d || !t_stop || !v_in || !v_out) return DRAG_ERR_NULL_POINTER;
+  const int64_t C = d->n_cells, ld = d->ld, N = d->n_species, D = d->n_dim;
+  const Range ro = span(v_out, D * (N + 1), ld, C);
+  if (overlap(ro, span(rho_g, 1, ld, C)) || overlap(ro, span(rho_d, N, ld, C)) ||
+      overlap(ro, span(t_stop, N, ld, C)))
+    return DRAG_ERR_ALIAS;
+  if ((const double*)v_out != v_in && overlap(ro, span(v_in, D * (N + 1), ld, C)))
+    return DRAG_ERR_ALIAS;
+  CellArgs A{rho_g, rho_d, t_stop, v_in, v_out, C, ld, d->dt, (int)D, d->k_max, d->option};
+  const int map = mapping_for((int)N);
+  return map == DRAG_MAP_LANE ? lane_fwd((int)N)(A, (hipStream_t)stream)
+                              : wave_fwd((int)N)(A, (hipStream_t)stream);
+}
+
+int drag_expm_apply_backward(const drag_desc* d, const double* rho_g, const double* rho_d,
+                             const double* t_stop, const double* v_in, const double* w,
+                             double*, double*, double*, double*, double*, drag_stream_t) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (d->n_cells == 0) return DRAG_OK;
+  if (!rho_g || !rho_d || !t_stop || !v_in || !w) return DRAG_ERR_NULL_POINTER;
+  return DRAG_ERR_PLAN;
+}
+
+int drag_plan_batched(const drag_batch_desc*, drag_plan** out) {
+  if (out) *out = nullptr;
+  return DRAG_ERR_PLAN;
+}
+int drag_plan_offsets(const drag_plan*, int64_t*, int64_t*, int64_t*, int64_t*) {
+  return DRAG_ERR_PLAN;
+}
+int drag_expm_apply_batched(drag_plan*, const double*, const double*, double*, drag_stream_t) {
+  return DRAG_ERR_PLAN;
+}
+int drag_plan_destroy(drag_plan*) { return DRAG_OK; }
+
+int drag_get_status(drag_stream_t stream, int32_t* host_status) {
+  if (!host_status) return DRAG_ERR_NULL_POINTER;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return DRAG_ERR_HIP;
+  unsigned v = 0;
+  e = hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_status_word), sizeof(v), 0, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return DRAG_ERR_HIP;
+  *host_status = (int32_t)v;
+  return DRAG_OK;
+}
+
+int drag_clear_status(drag_stream_t stream) {
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, (hipStream_t)stream);
+  return hip_status(hipGetLastError());
+}
+
+const char* drag_status_string(int code) {
+  switch (code) {
+    case DRAG_OK: return "ok";
+    case DRAG_ERR_NULL_DESC: return "descriptor pointer is NULL";
+    case DRAG_ERR_N_CELLS: return "n_cells < 0";
+    case DRAG_ERR_N_SPECIES: return "n_species outside [1, 16]";
+    case DRAG_ERR_N_DIM: return "n_dim outside [1, 3]";
+    case DRAG_ERR_LD: return "ld < n_cells or ld too large";
+    case DRAG_ERR_DT: return "dt is NaN, infinite or negative";
+    case DRAG_ERR_K_MAX: return "k_max outside [1, 9]";
+    case DRAG_ERR_OPTION: return "option not 0, 1 or 2";
+    case DRAG_ERR_NULL_POINTER: return "a required pointer is NULL";
+    case DRAG_ERR_ALIAS: return "an output overlaps an input";
+    case DRAG_ERR_PLAN: return "invalid batched plan or block table";
+    case DRAG_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status code";
+  }
+}
+
+int drag_table_row(int k, int32_t* m, int32_t* q, int32_t* r, double* theta) {
+  if (k < 1 || k > 9) return DRAG_ERR_K_MAX;
+  if (m) *m = kTabM[k];
+  if (q) *q = kTabQ[k];
+  if (r) *r = kTabR[k];
+  if (theta) *theta = kTheta[k];
+  return DRAG_OK;
+}
+
+int drag_select(double norm, int32_t k_max, int32_t option, int32_t* k, int32_t* m,
+                int32_t* s) {
+  if (k_max < 1 || k_max > 9) return DRAG_ERR_K_MAX;
+  if (option < 0 || option > 2) return DRAG_ERR_OPTION;
+  if (!(norm >= 0.0) || !isfinite(norm)) return DRAG_ERR_DT;
+  const Kms r = select_kms(norm, k_max, option);
+  if (k) *k = r.k;
+  if (m) *m = r.m;
+  if (s) *s = r.s;
+  return DRAG_OK;
+}
+
+int drag_set_mapping(int32_t n_species, int32_t mapping) {
+  if (n_species < 1 || n_species > kMaxSpecies) return DRAG_ERR_N_SPECIES;
+  if (mapping != DRAG_MAP_AUTO && mapping != DRAG_MAP_LANE && mapping != DRAG_MAP_WAVE)
+    return DRAG_ERR_OPTION;
+  if (mapping == DRAG_MAP_LANE && n_species > kLaneMaxN) return DRAG_ERR_OPTION;
+  g_map_override[n_species - 1] = mapping;
+  return DRAG_OK;
+}
+
+int drag_get_mapping(int32_t n_species, int32_t* mapping) {
+  if (n_species < 1 || n_species > kMaxSpecies) return DRAG_ERR_N_SPECIES;
+  if (!mapping) return DRAG_ERR_NULL_POINTER;
+  *mapping = mapping_for(n_species);
+  return DRAG_OK;
+}
+
+}  // extern "C"

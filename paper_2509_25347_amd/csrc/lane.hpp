@@ -1,0 +1,202 @@
+// lane.hpp -- one cell per lane (VALU), for small species counts N.
+//
+// Every lane owns one cell and keeps the N x N matrices of that cell in its
+// own VGPRs; all arithmetic is scalar FP64 with explicit fma().
+//
+// Reduced form.  The drag matrix A = dt K (velocity form: A00 = -sum e_i a_i,
+// A0i = e_i a_i, Ai0 = a_i, Aii = -a_i) has the right null vector 1 (its rows
+// sum to zero) and the left null vector rho (momentum, Sect. 2.1).  In the
+// coordinates (v_g, dv_i = v_i - v_g) it is block triangular, and the
+// relative velocities obey dv' = At dv with the N x N matrix
+//     At_jk = -a_j [j == k] - p_k,   p_k = e_k a_k,
+// while the gas velocity follows from conservation of total momentum
+// rho_g v_g + sum_i rho_i v_i.  For any polynomial T (the Taylor
+// approximant, and its 2^s-th power) T(A) acts exactly as T(At) on dv and as
+// momentum conservation on v_g, so with Z = T_m(2^-s At)^(2^s) - I,
+//     u      = Z dv,
+//     v_g'   = v_g - (e . u) / (1 + sum_i e_i),
+//     v_i'   = v_i + (v_g' - v_g) + u_i,
+// is the paper's approximant applied to v, up to rounding.  The scaling
+// s and degree m come from ||A||_1 of the full matrix (Alg. 1), exactly as
+// in the paper; the conserved mode no longer passes through the squarings.
+#pragma once
+
+#include "common.hpp"
+
+namespace dragexp {
+
+// Horner evaluation of F = sum_{i=1}^{m} c_i M^i = T_m(M) - I for the
+// structured M = 2^-s At: M_jk = -b_j [j == k] - pb_k.  Right products by M
+// cost O(N^2): (F M)_ik = -F_ik b_k - (sum_l F_il) pb_k.  Lanes of one
+// wavefront may have different m; the loop runs to the wavefront's largest
+// m and each lane adds only its own coefficients (a zero F stays zero).
+template <int N>
+__device__ __forceinline__ void lane_taylor(double (&F)[N][N], const double (&b)[N],
+                                            const double (&pb)[N], int m, int m_max) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < N; ++k) F[i][k] = 0.0;
+  for (int it = m_max; it >= 1; --it) {
+    const double c = (it <= m) ? kInvFact[it] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      F[i][i] += c;
+      double rs = 0.0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) rs += F[i][l];
+#pragma unroll
+      for (int k = 0; k < N; ++k) F[i][k] = fma(-F[i][k], b[k], -rs * pb[k]);
+    }
+  }
+}
+
+// One Y-form squaring Z <- 2 Z + Z Z (the paper's X <- X X with X = I + Z).
+template <int N>
+__device__ __forceinline__ void lane_square(double (&Z)[N][N]) {
+  double T[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double acc = 2.0 * Z[i][k];
+#pragma unroll
+      for (int l = 0; l < N; ++l) acc = fma(Z[i][l], Z[l][k], acc);
+      T[i][k] = acc;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < N; ++k) Z[i][k] = T[i][k];
+}
+
+__device__ __forceinline__ int wave_max_int(int x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+// Per-cell set-up: coefficients, ||A||_1 (bit-exact order), Alg. 1.
+template <int N>
+struct LaneCell {
+  double a[N], e[N], p[N];
+  double sigma;  // 1 + sum e_i
+  double nrm;
+  unsigned bad;
+  Kms kms;
+};
+
+template <int N>
+__device__ __forceinline__ void lane_setup(LaneCell<N>& C, const double* rho_g,
+                                           const double* rho_d, const double* t_stop,
+                                           int64_t ld, int64_t c, double dt, int K,
+                                           int option) {
+  const double rg = rho_g[c];
+  C.bad = gas_bad(rg);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double t = t_stop[i * ld + c];
+    const double r = rho_d[i * ld + c];
+    C.bad |= species_bad(t, r);
+    const Species sp = species_coeffs(dt, t, r, rg);
+    C.a[i] = sp.a;
+    C.e[i] = sp.e;
+    C.p[i] = sp.p;
+  }
+  // ||A||_1: the gas column |A00| + a_1 + .. + a_N, the species columns
+  // p_i + a_i; sums in ascending order, one rounding per operation.
+  double s = 0.0, sig = 1.0;
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    s = s + C.p[i];
+    sig = sig + C.e[i];
+    finite = finite && isfinite(C.a[i]) && isfinite(C.p[i]);
+  }
+  double nrm = s;
+#pragma unroll
+  for (int i = 0; i < N; ++i) nrm = nrm + C.a[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) nrm = fmax(nrm, C.p[i] + C.a[i]);
+  if (!C.bad && !(finite && isfinite(nrm))) C.bad |= kBadNorm;
+  C.sigma = sig;
+  C.nrm = nrm;
+  if (C.bad) {
+    // run the rest of the lane on a harmless zero matrix; outputs are NaN
+#pragma unroll
+    for (int i = 0; i < N; ++i) C.a[i] = C.e[i] = C.p[i] = 0.0;
+    C.sigma = 1.0;
+    nrm = 0.0;
+  }
+  C.kms = select_kms(nrm, K, option);
+}
+
+// Z = T_m(2^-s At)^(2^s) - I for the lane's cell.
+template <int N>
+__device__ __forceinline__ void lane_expm(double (&Z)[N][N], const LaneCell<N>& C) {
+  double b[N], pb[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    b[i] = ldexp(C.a[i], -C.kms.s);
+    pb[i] = ldexp(C.p[i], -C.kms.s);
+  }
+  const int m_max = wave_max_int(C.kms.m);
+  lane_taylor<N>(Z, b, pb, C.kms.m, m_max);
+  const int s_max = wave_max_int(C.kms.s);
+  for (int it = 0; it < s_max; ++it) {
+    if (it < C.kms.s) lane_square<N>(Z);
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_forward_lane(CellArgs A, int xcd_blocks) {
+  // XCD-aware order: consecutive workgroup ids go to different XCDs, so
+  // hand each XCD a contiguous range of cells.
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int64_t c = logical * 256 + threadIdx.x;
+  const bool active = c < A.n_cells;
+  const int64_t cc = active ? c : 0;  // inactive lanes shadow cell 0, store nothing
+
+  LaneCell<N> C;
+  lane_setup<N>(C, A.rho_g, A.rho_d, A.t_stop, A.ld, cc, A.dt, A.k_max, A.option);
+  double Z[N][N];
+  lane_expm<N>(Z, C);
+
+  const int n1 = N + 1;
+  // every velocity of the cell must be finite, else all its outputs are NaN
+  bool vfin = true;
+  for (int d = 0; d < A.n_dim; ++d) {
+#pragma unroll
+    for (int j = 0; j <= N; ++j) vfin = vfin && isfinite(A.v_in[(int64_t)(d * n1 + j) * A.ld + cc]);
+  }
+  if (!vfin && !C.bad) C.bad = kBadVelocity;
+  for (int d = 0; d < A.n_dim; ++d) {
+    double v[N + 1];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) v[j] = A.v_in[(int64_t)(d * n1 + j) * A.ld + cc];
+    double dv[N], u[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) dv[j] = v[j + 1] - v[0];
+    double eu = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc = fma(Z[i][k], dv[k], acc);
+      u[i] = acc;
+      eu = fma(C.e[i], acc, eu);
+    }
+    const double d0 = -eu / C.sigma;
+    if (active) {
+      const double qnan = __builtin_nan("");
+      A.v_out[(int64_t)(d * n1) * A.ld + c] = C.bad ? qnan : v[0] + d0;
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        A.v_out[(int64_t)(d * n1 + 1 + j) * A.ld + c] = C.bad ? qnan : v[j + 1] + (d0 + u[j]);
+    }
+  }
+  if (C.bad && active) atomicOr(&g_status_word, C.bad);
+}
+
+}  // namespace dragexp

@@ -1,0 +1,183 @@
+"""PyTorch-facing entry points of the drag update (argument marshalling only).
+
+Tensors must be float64 CUDA (HIP) tensors on one device; every array is
+passed as a raw device pointer with its leading dimension, and the work is
+enqueued on the current stream.  Layouts (cell index fastest):
+    rho_g [C], rho_d [N][C], t_stop [N][C], v [D][N+1][C]
+Views whose last stride is 1 and whose row stride is a common ``ld >= C``
+are accepted as they are.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+
+def _stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _require(t, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64 (got {t.dtype}); there is no implicit cast")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+
+
+def _ld_of(t, rows_dims, name):
+    """Leading dimension of an SoA array whose last axis is the cell axis."""
+    if t.stride(-1) != 1:
+        raise ValueError(f"{name}: the cell axis must be contiguous")
+    if t.dim() == 1:
+        return None
+    ld = t.stride(-2)
+    # all rows equally spaced by ld
+    exp = 1
+    for ax in range(t.dim() - 2, -1, -1):
+        if t.size(ax) > 1 and t.stride(ax) != ld * exp:
+            raise ValueError(f"{name}: rows must be equally spaced (stride ld)")
+        exp *= t.size(ax)
+    return ld
+
+
+def _shapes(rho_g, rho_d, t_stop, v):
+    for x, n in ((rho_g, "rho_g"), (rho_d, "rho_d"), (t_stop, "t_stop"), (v, "v")):
+        _require(x, n)
+    if rho_g.dim() != 1 or rho_d.dim() != 2 or t_stop.dim() != 2 or v.dim() != 3:
+        raise ValueError("expected rho_g [C], rho_d [N][C], t_stop [N][C], v [D][N+1][C]")
+    C = rho_g.size(0)
+    N = rho_d.size(0)
+    D = v.size(0)
+    if rho_d.shape != (N, C) or t_stop.shape != (N, C) or v.shape != (D, N + 1, C):
+        raise ValueError("inconsistent shapes")
+    if rho_g.stride(0) != 1:
+        raise ValueError("rho_g must be contiguous")
+    lds = {x for x in (_ld_of(rho_d, 1, "rho_d"), _ld_of(t_stop, 1, "t_stop"),
+                       _ld_of(v, 2, "v")) if x is not None}
+    if N == 1 and D == 1:
+        lds.add(C)
+    if len(lds) > 1:
+        raise ValueError("rho_d, t_stop and v must share one leading dimension")
+    ld = lds.pop() if lds else C
+    return C, N, D, max(ld, C) if C else max(ld, 1)
+
+
+def expm_apply(rho_g, rho_d, t_stop, v, dt, k_max=9, option=2, out=None, stream=None):
+    """v' = exp(dt K) v for every cell (drag_expm_apply).  ``out`` may be
+    ``v`` itself (in place)."""
+    C, N, D, ld = _shapes(rho_g, rho_d, t_stop, v)
+    if out is None:
+        out = torch.empty_like(v)
+    else:
+        _require(out, "out")
+        if out.shape != v.shape or _ld_of(out, 2, "out") not in (None, ld) and C:
+            raise ValueError("out must have the shape and layout of v")
+    desc = _lib.make_desc(C, N, D, ld, dt, k_max, option)
+    _lib.check(_lib.lib().drag_expm_apply(ctypes.byref(desc), _ptr(rho_g), _ptr(rho_d),
+                                          _ptr(t_stop), _ptr(v), _ptr(out),
+                                          _stream_ptr(stream)), "drag_expm_apply")
+    return out
+
+
+def build(rho_g, rho_d, t_stop, dt, k_max=9, option=2, stream=None):
+    """Per-cell a = dt/t, e = rho_i/rho_g, ||dt K||_1 and (k*, m*, s*)."""
+    for x, n in ((rho_g, "rho_g"), (rho_d, "rho_d"), (t_stop, "t_stop")):
+        _require(x, n)
+    C = rho_g.size(0)
+    N = rho_d.size(0)
+    ld = _ld_of(rho_d, 1, "rho_d") or C
+    dev = rho_g.device
+    a = torch.empty((N, C), dtype=torch.float64, device=dev)
+    e = torch.empty((N, C), dtype=torch.float64, device=dev)
+    nrm = torch.empty(C, dtype=torch.float64, device=dev)
+    k = torch.empty(C, dtype=torch.int32, device=dev)
+    m = torch.empty(C, dtype=torch.int32, device=dev)
+    s = torch.empty(C, dtype=torch.int32, device=dev)
+    if ld != C:
+        raise ValueError("build() takes contiguous [N][C] inputs")
+    desc = _lib.make_desc(C, N, 1, C, dt, k_max, option)
+    _lib.check(_lib.lib().drag_build(ctypes.byref(desc), _ptr(rho_g), _ptr(rho_d),
+                                     _ptr(t_stop), _ptr(a), _ptr(e), _ptr(nrm), _ptr(k),
+                                     _ptr(m), _ptr(s), _stream_ptr(stream)), "drag_build")
+    return a, e, nrm, k, m, s
+
+
+def expm_apply_backward(rho_g, rho_d, t_stop, v, grad_out, dt, k_max=9, option=2,
+                        want_v_out=True, want_grad_rho_g=True, stream=None):
+    """Fused forward + adjoint (drag_expm_apply_backward).
+
+    Returns (v_out or None, grad_v, grad_log_t, grad_rho_d, grad_rho_g or None).
+    """
+    C, N, D, ld = _shapes(rho_g, rho_d, t_stop, v)
+    _require(grad_out, "grad_out")
+    if grad_out.shape != v.shape:
+        raise ValueError("grad_out must have the shape of v")
+    if ld != C or not (v.is_contiguous() and grad_out.is_contiguous()):
+        raise ValueError("expm_apply_backward takes contiguous inputs")
+    dev = v.device
+    v_out = torch.empty_like(v) if want_v_out else None
+    g_v = torch.empty_like(v)
+    g_logt = torch.empty((N, C), dtype=torch.float64, device=dev)
+    g_rho = torch.empty((N, C), dtype=torch.float64, device=dev)
+    g_rho_g = torch.empty(C, dtype=torch.float64, device=dev) if want_grad_rho_g else None
+    desc = _lib.make_desc(C, N, D, C, dt, k_max, option)
+    _lib.check(_lib.lib().drag_expm_apply_backward(
+        ctypes.byref(desc), _ptr(rho_g), _ptr(rho_d), _ptr(t_stop), _ptr(v), _ptr(grad_out),
+        _ptr(v_out), _ptr(g_v), _ptr(g_logt), _ptr(g_rho), _ptr(g_rho_g),
+        _stream_ptr(stream)), "drag_expm_apply_backward")
+    return v_out, g_v, g_logt, g_rho, g_rho_g
+
+
+def get_status(stream=None) -> int:
+    st = ctypes.c_int32()
+    _lib.check(_lib.lib().drag_get_status(_stream_ptr(stream), ctypes.byref(st)),
+               "drag_get_status")
+    return st.value
+
+
+def clear_status(stream=None) -> None:
+    _lib.check(_lib.lib().drag_clear_status(_stream_ptr(stream)), "drag_clear_status")
+
+
+class DragExpm(torch.autograd.Function):
+    """v' = exp(dt K(t_stop, rho_d, rho_g)) v with the hand-written adjoint.
+
+    Only the inputs are saved; the backward recomputes the Taylor stage and
+    the squarings (drag_expm_apply_backward).  Gradients flow to t_stop
+    (through log t), rho_d, rho_g and v; dt, k_max and option get None.
+    """
+
+    @staticmethod
+    def forward(ctx, rho_g, rho_d, t_stop, v, dt, k_max, option):
+        ctx.save_for_backward(rho_g, rho_d, t_stop, v)
+        ctx.dt, ctx.k_max, ctx.option = dt, k_max, option
+        return expm_apply(rho_g, rho_d, t_stop, v, dt, k_max, option)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        rho_g, rho_d, t_stop, v = ctx.saved_tensors
+        _, g_v, g_logt, g_rho, g_rho_g = expm_apply_backward(
+            rho_g, rho_d, t_stop, v, grad_out.contiguous(), ctx.dt, ctx.k_max, ctx.option,
+            want_v_out=False)
+        # d/dt_i = d/dlog t_i / t_i
+        g_t = g_logt / t_stop if ctx.needs_input_grad[2] else None
+        return (g_rho_g if ctx.needs_input_grad[0] else None,
+                g_rho if ctx.needs_input_grad[1] else None,
+                g_t,
+                g_v if ctx.needs_input_grad[3] else None,
+                None, None, None)
+
+
+def drag_expm(rho_g, rho_d, t_stop, v, dt, k_max=9, option=2):
+    """Differentiable v' = exp(dt K) v (see DragExpm)."""
+    return DragExpm.apply(rho_g, rho_d, t_stop, v, dt, k_max, option)
