@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the drag update v' = exp(dt K) v on one MI355X.
+
+One step = one drag update of every cell of the workload (drag_expm_apply:
+coefficients, ||dt K||_1, Alg. 1, Taylor stage, squarings, apply), with all
+inputs resident in HBM before the timed region.  The default workload is the
+stiff N = 16 case the headline metric is quoted on: 2^20 cells, 16 dust
+species log-spaced over [1e-6, 1e2] dt, 3 velocity components, FP64.
+
+Printed: one JSON line with the throughput in cell-updates/s, the roofline
+of the dominant kernel (algorithmic FP64 flops per launch over the launch
+time, both measured here with HIP events on the launch stream) and the
+oracle's rate on the host as a reported CPU baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix), public spec
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, public spec
+METRIC = "FP64 cell-updates/s of exp(dt·K)·v at N=16, %FP64 peak; fwd+bwd vs fwd"
+
+TABLE_Q = {1: 1, 2: 2, 3: 2, 4: 3, 5: 3, 6: 4, 7: 4, 8: 5, 9: 5}
+TABLE_R = {1: 2, 2: 2, 3: 3, 4: 3, 5: 4, 6: 4, 7: 5, 8: 5, 9: 6}
+
+
+def algorithmic_flops(k, m, s, N, D):
+    """FP64 flops of the paper's method per cell in its dense (N+1) form:
+    (r-1+s) dense products 2n^3 (Horner and squarings), (q-1) powers of the
+    arrowhead matrix 2n(3n-2), the Paterson-Stockmeyer sums 2 m n^2 and the
+    apply 2 D n^2, with n = N + 1."""
+    n = N + 1
+    q = np.vectorize(TABLE_Q.get)(k)
+    r = np.vectorize(TABLE_R.get)(k)
+    return ((r - 1 + s) * 2.0 * n ** 3 + (q - 1) * 2.0 * n * (3 * n - 2)
+            + 2.0 * m * n ** 2 + 2.0 * D * n ** 2)
+
+
+def executed_flops(k, m, s, N, D, mapping):
+    """FP64 flops the library executes per cell: the same products on the
+    N x N relative-velocity block (16 x 16 MFMA tiles for the wave kernel)."""
+    q = np.vectorize(TABLE_Q.get)(k)
+    r = np.vectorize(TABLE_R.get)(k)
+    if mapping == "wave":
+        t = 16
+        return (r - 1 + s + q - 1 + 1) * 2.0 * t ** 3 + 2.0 * m * t * t
+    return (s * 2.0 * N ** 3 + m * 4.0 * N * N + 2.0 * D * N * N)
+
+
+def algorithmic_bytes(C, N, D):
+    """HBM bytes one step must move: read rho_g, rho_d, t_stop, v; write v'."""
+    return 8.0 * C * (1 + 2 * N + 2 * D * (N + 1))
+
+
+def cpu_baseline(d, budget_s=12.0, chunk=4096):
+    """The oracle (single thread) on a bounded prefix of the same workload."""
+    import oracle
+    oracle.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
+    C = d["rho_g"].shape[0]
+    done, t_used = 0, 0.0
+    while done < C and t_used < budget_s:
+        sl = slice(done, min(C, done + chunk))
+        t0 = time.perf_counter()
+        oracle.apply_cells(d["rho_g"][sl], d["rho_d"][:, sl], d["t_stop"][:, sl],
+                           d["v"][:, :, sl], d["dt"])
+        t_used += time.perf_counter() - t0
+        done = sl.stop
+    return {"value": done / t_used, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} cells of the workload, single thread, {t_used:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="n16_stiff_3d")
+    ap.add_argument("--cells", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the other workloads and the fused adjoint")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the drag update is cell-local and would shard by cell ranges)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_25347_amd import _lib, ops, workloads
+
+    _lib.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    name = args.workload
+    d = workloads.make(name, args.cells)
+    C = d["rho_g"].shape[0]
+    N = d["rho_d"].shape[0]
+    D = d["v"].shape[0]
+    T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
+    out = torch.empty_like(T["v"])
+    mapping = {1: "lane", 2: "wave"}[_lib.get_mapping(N)]
+
+    # per-cell (k*, m*, s*) for the flop count (outside the timed region)
+    _, _, _, kk, mm, ss = ops.build(T["rho_g"], T["rho_d"], T["t_stop"], d["dt"])
+    kk, mm, ss = (x.cpu().numpy() for x in (kk, mm, ss))
+    f_alg = float(algorithmic_flops(kk, mm, ss, N, D).sum())
+    f_exe = float(executed_flops(kk, mm, ss, N, D, mapping).sum())
+    b_alg = algorithmic_bytes(C, N, D)
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"], out=out)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"], out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / args.steps
+    value = C * args.steps / (ms_total * 1e-3)
+
+    achieved_tflops = f_alg / (ms_per_step * 1e-3) / 1e12
+    roof = {
+        "bound": "mfma" if mapping == "wave" else "alu",
+        "achieved": round(achieved_tflops, 3),
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tflops / FP64_PEAK_TFLOPS, 4),
+        "traffic": None,
+        "kernel": f"k_forward_{mapping}<{N}>",
+        "flops_per_launch": f_alg,
+        "executed_flops_per_launch": f_exe,
+        "executed_frac": round(f_exe / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        "hbm_bytes_per_launch": b_alg,
+        "hbm_frac": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "n_cells": C, "n_species": N, "n_dim": D,
+                   "dt": d["dt"], "k_max": 9, "option": 2, "mapping": mapping,
+                   "s_star": [int(ss.min()), int(ss.max())],
+                   "m_star": [int(mm.min()), int(mm.max())]},
+        "roofline": roof,
+        "wall_s_timed": wall,
+    }
+    if args.extra:
+        res["extra"] = extra_measurements(torch, ops, workloads, dev, d, T, out, args)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(d)
+    print(json.dumps(res), flush=True)
+
+
+def _time(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def extra_measurements(torch, ops, workloads, dev, d, T, out, args):
+    ex = {}
+    for name in ("n4_3d", "n8_adjoint_3d", "n1_closed_form"):
+        dd = workloads.make(name)
+        TT = {k: torch.from_numpy(dd[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
+        oo = torch.empty_like(TT["v"])
+        ms = _time(torch, lambda: ops.expm_apply(TT["rho_g"], TT["rho_d"], TT["t_stop"], TT["v"],
+                                                 dd["dt"], out=oo), 20, 3)
+        ex[name] = {"ms": ms, "cells_per_s": dd["rho_g"].shape[0] / (ms * 1e-3)}
+    return ex
+
+
+if __name__ == "__main__":
+    main()

@@ -22,6 +22,8 @@ HEADERS = [os.path.join(ROOT, "include", "dragexp.h")] + [
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off",
+    # MFMA accumulators in ordinary VGPRs: no AGPR round trips around chains
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

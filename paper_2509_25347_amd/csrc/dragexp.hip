@@ -131,7 +131,7 @@ static FwdFn lane_fwd(int N) {
 // drag_set_mapping.
 static int g_default_map[16] = {
     DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
-    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
+    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
 static int g_map_override[16] = {0};
