@@ -117,21 +117,26 @@ int drag_expm_apply(const drag_desc *desc, const double *rho_g,
  * drag_expm_apply_backward -- the adjoint of drag_expm_apply for the loss
  * L = sum_{d,j,c} grad_v_out[d][j][c] * v_out[d][j][c] (the chain rule of a
  * training step: grad_v_out = dL/dv_out).  The exponential is differentiated
- * with (k*, m*, s*) held fixed; nothing is stored between forward and
- * backward: the Taylor stage and the squaring chain are recomputed.
+ * with (k*, m*, s*) held fixed, as the Frechet derivative of the same Taylor
+ * scaling-and-squaring approximant (Sect. 2.3, Appendix B); nothing is
+ * stored between forward and backward: the Taylor stage and the squaring
+ * chain are recomputed alongside their derivatives.
  *   v_out       [D][N+1][ld] or NULL: the forward result (fused forward)
  *   grad_v_in   [D][N+1][ld] or NULL: dL/dv_in
  *   grad_log_t  [N][ld] or NULL:      dL/d(log t_i)
+ *   grad_t_stop [N][ld] or NULL:      dL/d t_i  (= dL/d(log t_i) / t_i)
  *   grad_rho_d  [N][ld] or NULL:      dL/d rho_i
  *   grad_rho_g  [C] or NULL:          dL/d rho_g
- * No output may overlap an input or another output.
+ * No output may overlap an input or another output.  Bad cells get NaN in
+ * every output, as in drag_expm_apply.
  */
 int drag_expm_apply_backward(const drag_desc *desc, const double *rho_g,
                              const double *rho_d, const double *t_stop,
                              const double *v_in, const double *grad_v_out,
                              double *v_out, double *grad_v_in,
-                             double *grad_log_t, double *grad_rho_d,
-                             double *grad_rho_g, drag_stream_t stream);
+                             double *grad_log_t, double *grad_t_stop,
+                             double *grad_rho_d, double *grad_rho_g,
+                             drag_stream_t stream);
 
 /* ---- batched blocks with uneven species counts -------------------------- */
 /*

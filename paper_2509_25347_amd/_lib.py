@@ -120,7 +120,7 @@ def lib():
     L.drag_build.restype = ctypes.c_int
     L.drag_expm_apply.argtypes = [desc_p] + [vp] * 5 + [vp]
     L.drag_expm_apply.restype = ctypes.c_int
-    L.drag_expm_apply_backward.argtypes = [desc_p] + [vp] * 10 + [vp]
+    L.drag_expm_apply_backward.argtypes = [desc_p] + [vp] * 11 + [vp]
     L.drag_expm_apply_backward.restype = ctypes.c_int
     L.drag_plan_batched.argtypes = [P(DragBatchDesc), P(vp)]
     L.drag_plan_batched.restype = ctypes.c_int

@@ -1,0 +1,487 @@
+// adjoint.hpp -- fused forward + adjoint of v' = exp(dt K) v.
+//
+// Loss L = sum_{c,j} w[c][j] v'[c][j] (w = dL/dv', c the velocity component).
+// In the relative-velocity form (lane.hpp) with W_c = sum_j w[c][j],
+//     L = sum_c ( w_c . v_c + ubar_c . (Z dv_c) ),
+//     ubar_c[i] = w_c[1+i] - W_c e_i / sigma,
+// so Z enters through <G, Z> with G = sum_c ubar_c dv_c^T, and
+//     dL/dAt = L_R(At^T, G),
+// the Frechet derivative of the approximant R(X) = T_m(2^-s X)^(2^s) at At^T
+// in the direction G (the adjoint of a real matrix polynomial's derivative is
+// its derivative at the transpose).  It is evaluated forward-mode alongside
+// R(At^T) itself, with (k*, m*, s*) held fixed and nothing stored:
+//     B = 2^-s At^T,  dB = 2^-s G,
+//     powers        P_j = B P_{j-1},  dP_j = dB P_{j-1} + B dP_{j-1},
+//     Horner        F <- Bbar_k + F P_q,  dF <- dBbar_k + dF P_q + F dP_q,
+//     squarings     Y <- 2Y + Y Y,        dY <- 2dY + dY Y + Y dY.
+// At the end Y = Z^T (the forward result, transposed) and dY = dL/dAt.  The
+// chain rule through At_jk = -a_j [j == k] - e_k a_k, a = dt/t, e = rho/rho_g
+// and the direct dependence of the gas update on e gives the parameter
+// gradients; dL/dv follows from dv = v_dust - v_gas and Z^T ubar.
+#pragma once
+
+#include "common.hpp"
+#include "lane.hpp"
+#include "wave.hpp"
+
+namespace dragexp {
+
+// ---- one cell per lane --------------------------------------------------------
+
+template <int N>
+__global__ void __launch_bounds__(256) k_backward_lane(BackArgs A, int xcd_blocks) {
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int64_t c = logical * 256 + threadIdx.x;
+  const bool active = c < A.n_cells;
+  const int64_t cc = active ? c : 0;
+  const int64_t ld = A.ld;
+  const int n1 = N + 1;
+  const int D = A.n_dim;
+
+  LaneCell<N> C;
+  lane_setup<N>(C, A.rho_g, A.rho_d, A.t_stop, ld, cc, A.dt, A.k_max, A.option);
+  bool fin = true;
+  for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+      const int64_t idx = (int64_t)(d * n1 + j) * ld + cc;
+      fin = fin && isfinite(A.v_in[idx]) && isfinite(A.w[idx]);
+    }
+  }
+  if (!fin && !C.bad) {
+    C.bad = kBadVelocity;
+#pragma unroll
+    for (int i = 0; i < N; ++i) C.a[i] = C.e[i] = C.p[i] = 0.0;
+    C.sigma = 1.0;
+    C.kms = select_kms(0.0, A.k_max, A.option);
+  }
+  const int s = C.kms.s;
+
+  // dB = 2^-s G, G = sum_c ubar_c dv_c^T
+  double dB[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < N; ++k) dB[i][k] = 0.0;
+  if (!C.bad) {
+    for (int d = 0; d < D; ++d) {
+      double v[N + 1], w[N + 1];
+#pragma unroll
+      for (int j = 0; j <= N; ++j) {
+        const int64_t idx = (int64_t)(d * n1 + j) * ld + cc;
+        v[j] = A.v_in[idx];
+        w[j] = A.w[idx];
+      }
+      double W = 0.0;
+#pragma unroll
+      for (int j = 0; j <= N; ++j) W += w[j];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const double ub = w[i + 1] - W * C.e[i] / C.sigma;
+#pragma unroll
+        for (int k = 0; k < N; ++k) dB[i][k] = fma(ub, v[k + 1] - v[0], dB[i][k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < N; ++k) dB[i][k] = ldexp(dB[i][k], -s);
+
+  double b[N], pb[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    b[i] = ldexp(C.a[i], -s);
+    pb[i] = ldexp(C.p[i], -s);
+  }
+
+  // Taylor stage and its derivative, Horner in B = M^T:
+  // B_jk = -b_j [j == k] - pb_j, so (H B)_ik = -H_ik b_k - (H pb)_i.
+  double Y[N][N], dY[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int k = 0; k < N; ++k) Y[i][k] = dY[i][k] = 0.0;
+  const int m_max = wave_max_int(C.kms.m);
+  for (int it = m_max; it >= 1; --it) {
+    const double cf = (it <= C.kms.m) ? kInvFact[it] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double h[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) h[k] = Y[i][k] + (k == i ? cf : 0.0);
+      double hp = 0.0, fp = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        hp = fma(h[k], pb[k], hp);
+        fp = fma(dY[i][k], pb[k], fp);
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        double acc = fma(-dY[i][k], b[k], -fp);
+#pragma unroll
+        for (int l = 0; l < N; ++l) acc = fma(h[l], dB[l][k], acc);
+        dY[i][k] = acc;
+        Y[i][k] = fma(-h[k], b[k], -hp);
+      }
+    }
+  }
+
+  // squarings with the Frechet recurrence
+  const int s_max = wave_max_int(s);
+  for (int it = 0; it < s_max; ++it) {
+    if (it < s) {
+      double T[N][N];
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          double acc = 2.0 * dY[i][k];
+#pragma unroll
+          for (int l = 0; l < N; ++l) {
+            acc = fma(dY[i][l], Y[l][k], acc);
+            acc = fma(Y[i][l], dY[l][k], acc);
+          }
+          T[i][k] = acc;
+        }
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) dY[i][k] = T[i][k];
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          double acc = 2.0 * Y[i][k];
+#pragma unroll
+          for (int l = 0; l < N; ++l) acc = fma(Y[i][l], Y[l][k], acc);
+          T[i][k] = acc;
+        }
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int k = 0; k < N; ++k) Y[i][k] = T[i][k];
+    }
+  }
+
+  // outputs: Y = Z^T, dY = dL/dAt.  The species coefficients are recomputed
+  // from the inputs (same roundings) so they need not stay live in VGPRs
+  // through the squarings.
+  const double qnan = __builtin_nan("");
+  const double rg = A.rho_g[cc];
+  double ea[N], aa[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const Species sp = species_coeffs(A.dt, A.t_stop[k * ld + cc], A.rho_d[k * ld + cc], rg);
+    ea[k] = C.bad ? 0.0 : sp.e;
+    aa[k] = C.bad ? 0.0 : sp.a;
+  }
+  const double sigma = C.sigma;
+  double ge_dir[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) ge_dir[k] = 0.0;
+  for (int d = 0; d < D; ++d) {
+    double v[N + 1], w[N + 1];
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+      const int64_t idx = (int64_t)(d * n1 + j) * ld + cc;
+      v[j] = A.v_in[idx];
+      w[j] = A.w[idx];
+    }
+    double W = 0.0;
+#pragma unroll
+    for (int j = 0; j <= N; ++j) W += w[j];
+    double dv[N], u[N], ub[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) dv[k] = v[k + 1] - v[0];
+    double eu = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc = fma(Y[k][i], dv[k], acc);  // (Z dv)_i
+      u[i] = acc;
+      eu = fma(ea[i], acc, eu);
+      ub[i] = w[i + 1] - W * ea[i] / sigma;
+    }
+    const double d0 = -eu / sigma;
+    double zt_sum = 0.0, zt[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc = fma(Y[j][k], ub[k], acc);  // (Z^T ubar)_j
+      zt[j] = acc;
+      zt_sum += acc;
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) ge_dir[k] = fma(-d0 - u[k], W / sigma, ge_dir[k]);
+    if (active) {
+      if (A.v_out) {
+        A.v_out[(int64_t)(d * n1) * ld + c] = C.bad ? qnan : v[0] + d0;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+          A.v_out[(int64_t)(d * n1 + 1 + j) * ld + c] = C.bad ? qnan : v[j + 1] + (d0 + u[j]);
+      }
+      if (A.g_v) {
+        A.g_v[(int64_t)(d * n1) * ld + c] = C.bad ? qnan : w[0] - zt_sum;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+          A.g_v[(int64_t)(d * n1 + 1 + j) * ld + c] = C.bad ? qnan : w[j + 1] + zt[j];
+      }
+    }
+  }
+  if (active) {
+    double sum_ege = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double col = 0.0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) col += dY[j][k];
+      const double ga = -dY[k][k] - ea[k] * col;
+      const double ge = -aa[k] * col + ge_dir[k];
+      const double glt = -aa[k] * ga;
+      sum_ege = fma(ea[k], ge, sum_ege);
+      if (A.g_logt) A.g_logt[k * ld + c] = C.bad ? qnan : glt;
+      if (A.g_t) A.g_t[k * ld + c] = C.bad ? qnan : glt / A.t_stop[k * ld + c];
+      if (A.g_rho_d) A.g_rho_d[k * ld + c] = C.bad ? qnan : ge / rg;
+    }
+    if (A.g_rho_g) A.g_rho_g[c] = C.bad ? qnan : -sum_ege / rg;
+    if (C.bad) atomicOr(&g_status_word, C.bad);
+  }
+}
+
+// ---- one cell per wavefront, FP64 MFMA ---------------------------------------------
+
+__device__ __forceinline__ double group16_sum(double x) {
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ __forceinline__ double groups_sum(double x) {
+  x += __shfl_xor(x, 16, 64);
+  x += __shfl_xor(x, 32, 64);
+  return x;
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_backward_wave(BackArgs A, int xcd_blocks) {
+  __shared__ double lds[4 * 3 * kStageDoubles];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, j = lane & 15;
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int64_t cell = logical * 4 + w;
+  if (cell >= A.n_cells) return;  // uniform over the wavefront
+  double* bufX = lds + (3 * w) * kStageDoubles;
+  double* bufY = bufX + kStageDoubles;
+  double* bufZ = bufY + kStageDoubles;
+  const int64_t ld = A.ld;
+  const int n1 = N + 1;
+  const int D = A.n_dim;
+  const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
+
+  WaveCell<N> Wc;
+  wave_setup<N>(Wc, A.rho_g, A.rho_d, A.t_stop, ld, cell, A.dt, A.k_max, A.option, j);
+
+  // velocity data in the component-species layout: lane (g = component c,
+  // j = species) holds the cell's values of component c for species j
+  const bool cj = (g < D) && (j < N);
+  double v0 = 0.0, vj = 0.0, w0 = 0.0, wj = 0.0;
+  bool fin = true;
+  if (g < D) {
+    const int64_t base = (int64_t)(g * n1) * ld + cell;
+    v0 = A.v_in[base];
+    w0 = A.w[base];
+    fin = isfinite(v0) && isfinite(w0);
+    if (j < N) {
+      vj = A.v_in[base + (int64_t)(1 + j) * ld];
+      wj = A.w[base + (int64_t)(1 + j) * ld];
+      fin = fin && isfinite(vj) && isfinite(wj);
+    }
+  }
+  const unsigned bad = Wc.bad | (__all(fin) ? 0u : kBadVelocity);
+  if (bad) {
+    const double qnan = __builtin_nan("");
+    if (lane < D * n1) {
+      if (A.v_out) A.v_out[(int64_t)lane * ld + cell] = qnan;
+      if (A.g_v) A.g_v[(int64_t)lane * ld + cell] = qnan;
+    }
+    if (lane < N) {
+      if (A.g_logt) A.g_logt[lane * ld + cell] = qnan;
+      if (A.g_t) A.g_t[lane * ld + cell] = qnan;
+      if (A.g_rho_d) A.g_rho_d[lane * ld + cell] = qnan;
+    }
+    if (lane == 0) {
+      if (A.g_rho_g) A.g_rho_g[cell] = qnan;
+      atomicOr(&g_status_word, bad);
+    }
+    return;
+  }
+
+  const double Wsum = w0 + group16_sum(cj ? wj : 0.0);  // W_c of this lane's component
+  const double dv = cj ? vj - v0 : 0.0;
+  const double ub = cj ? wj - Wsum * Wc.ej / Wc.sigma : 0.0;
+
+  const int s = Wc.kms.s;
+  const int q = kTabQ[Wc.kms.k], r = kTabR[Wc.kms.k];
+  const double bj = ldexp(Wc.aj, -s), pbj = ldexp(Wc.pj, -s);
+
+  // dB = 2^-s G, G = Ubar dV^T: one MFMA with k = the velocity component
+  v4d dB = __builtin_amdgcn_mfma_f64_16x16x4f64(ub, dv, zero4, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) dB[v] = ldexp(dB[v], -s);
+
+  // B = M^T: B[row][col] = -b_row [row == col] - pb_row
+  v4d Bm;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = 4 * v + g;
+    const double pbr = __shfl(pbj, row, 64);
+    Bm[v] = (row < N && j < N) ? ((row == j ? -bj : 0.0) - pbr) : 0.0;
+  }
+  double BmA[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int col = 4 * t + g;
+    BmA[t] = (j < N && col < N) ? ((j == col ? -bj : 0.0) - pbj) : 0.0;
+  }
+  double dBA[4];
+  stage_tile(bufZ, g, j, dB);
+  load_a_ops(bufZ, g, j, dBA);
+
+  // powers and their derivatives
+  v4d P[6], dP[6];
+  P[1] = Bm;
+  dP[1] = dB;
+#pragma unroll
+  for (int jj = 2; jj <= 5; ++jj) {
+    if (jj <= q) {
+      double Bp[4], Bdp[4];
+      stage_tile(bufX, g, j, P[jj - 1]);
+      stage_tile(bufY, g, j, dP[jj - 1]);
+      load_b_ops(bufX, g, j, Bp);
+      load_b_ops(bufY, g, j, Bdp);
+      P[jj] = mma16(BmA, Bp, zero4);
+      dP[jj] = mma16(dBA, Bp, zero4);
+      dP[jj] = mma16(BmA, Bdp, dP[jj]);
+    } else {
+      P[jj] = zero4;
+      dP[jj] = zero4;
+    }
+  }
+  v4d Pq = P[1], dPq = dP[1];
+#pragma unroll
+  for (int jj = 2; jj <= 5; ++jj)
+    if (jj == q) {
+      Pq = P[jj];
+      dPq = dP[jj];
+    }
+  auto comb = [&](const v4d (&X)[6], int k) {
+    v4d acc = zero4;
+#pragma unroll
+    for (int jj = 1; jj <= 5; ++jj) {
+      if (jj <= q) {
+        const double cf = kInvFact[q * k + jj];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = fma(cf, X[jj][v], acc[v]);
+      }
+    }
+    return acc;
+  };
+
+  // Horner
+  double Bq[4], dBq[4];
+  stage_tile(bufX, g, j, Pq);
+  stage_tile(bufY, g, j, dPq);
+  load_b_ops(bufX, g, j, Bq);
+  load_b_ops(bufY, g, j, dBq);
+  v4d F = comb(P, r - 1), dF = comb(dP, r - 1);
+  for (int k = r - 2; k >= 0; --k) {
+    double AF[4], AdF[4];
+    stage_tile(bufX, g, j, F);
+    stage_tile(bufY, g, j, dF);
+    load_a_ops(bufX, g, j, AF);
+    load_a_ops(bufY, g, j, AdF);
+    const v4d Fn = mma16(AF, Bq, comb(P, k));
+    v4d dFn = mma16(AdF, Bq, comb(dP, k));
+    dF = mma16(AF, dBq, dFn);
+    F = Fn;
+  }
+
+  // squarings with the Frechet recurrence
+  v4d Y = F, dY = dF;
+  for (int it = 0; it < s; ++it) {
+    double AY[4], BY[4], AdY[4], BdY[4];
+    stage_tile(bufX, g, j, Y);
+    stage_tile(bufY, g, j, dY);
+    load_a_ops(bufX, g, j, AY);
+    load_b_ops(bufX, g, j, BY);
+    load_a_ops(bufY, g, j, AdY);
+    load_b_ops(bufY, g, j, BdY);
+    const v4d Yn = mma16(AY, BY, Y + Y);
+    v4d dYn = mma16(AdY, BY, dY + dY);
+    dY = mma16(AY, BdY, dYn);
+    Y = Yn;
+  }
+
+  // Y = Z^T, dY = dL/dAt.  u_c = Z dv_c = (dV^T Y)[c];  Z^T ubar_c = (Ubar^T Z)[c]
+  double YB[4], ZB[4], DvA[4], UbA[4];
+  stage_tile(bufX, g, j, Y);
+  load_b_ops(bufX, g, j, YB);   // Y as the B operand
+  load_a_ops(bufX, g, j, ZB);   // Z = Y^T as the B operand
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    // A operand rows are components: lane (g, i) takes component i, species 4t+g
+    const int src = (j < D) ? 16 * j + 4 * t + g : 0;
+    const double a1 = __shfl(dv, src, 64), a2 = __shfl(ub, src, 64);
+    DvA[t] = (j < D) ? a1 : 0.0;
+    UbA[t] = (j < D) ? a2 : 0.0;
+  }
+  const v4d Um = mma16(DvA, YB, zero4);   // lane (g, j) [0]: u_g[j]
+  const v4d Vm = mma16(UbA, ZB, zero4);   // lane (g, j) [0]: (Z^T ubar_g)_j
+  const double u = cj ? Um[0] : 0.0;
+  const double zt = cj ? Vm[0] : 0.0;
+  const double eu = group16_sum(Wc.ej * u);
+  const double d0 = -eu / Wc.sigma;
+  const double zt_sum = group16_sum(zt);
+  if (g < D) {
+    const int64_t base = (int64_t)(g * n1) * ld + cell;
+    if (A.v_out) {
+      if (j < N) A.v_out[base + (int64_t)(1 + j) * ld] = vj + (d0 + u);
+      if (j == 0) A.v_out[base] = v0 + d0;
+    }
+    if (A.g_v) {
+      if (j < N) A.g_v[base + (int64_t)(1 + j) * ld] = wj + zt;
+      if (j == 0) A.g_v[base] = w0 - zt_sum;
+    }
+  }
+  // direct dependence of the gas update on e, summed over components
+  const double ge_dir = groups_sum(cj ? (-d0 - u) * (Wsum / Wc.sigma) : 0.0);
+  // column sums and diagonal of dL/dAt (D layout: rows 4v+g of column j)
+  double col = dY[0] + dY[1] + dY[2] + dY[3];
+  col = groups_sum(col);
+  double dg = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (4 * v + g == j) dg = dY[v];
+  dg = groups_sum(dg);
+  if (g == 0) {
+    const double rg = A.rho_g[cell];
+    double ge = 0.0;
+    if (j < N) {
+      const double ga = -dg - Wc.ej * col;
+      ge = -Wc.aj * col + ge_dir;
+      const double glt = -Wc.aj * ga;
+      if (A.g_logt) A.g_logt[j * ld + cell] = glt;
+      if (A.g_t) A.g_t[j * ld + cell] = glt / A.t_stop[j * ld + cell];
+      if (A.g_rho_d) A.g_rho_d[j * ld + cell] = ge / rg;
+    }
+    const double sum_ege = group16_sum(Wc.ej * ge);
+    if (j == 0 && A.g_rho_g) A.g_rho_g[cell] = -sum_ege / rg;
+  }
+}
+
+}  // namespace dragexp

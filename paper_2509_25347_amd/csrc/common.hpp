@@ -145,6 +145,7 @@ struct BackArgs {
   double* v_out;
   double* g_v;
   double* g_logt;
+  double* g_t;
   double* g_rho_d;
   double* g_rho_g;
   int64_t n_cells;

@@ -13,6 +13,7 @@
 #include "common.hpp"
 #include "lane.hpp"
 #include "wave.hpp"
+#include "adjoint.hpp"
 
 namespace dragexp {
 
@@ -107,6 +108,40 @@ static int launch_forward_wave(const CellArgs& A, hipStream_t st) {
 }
 
 using FwdFn = int (*)(const CellArgs&, hipStream_t);
+using BwdFn = int (*)(const BackArgs&, hipStream_t);
+
+template <int N>
+static int launch_backward_lane(const BackArgs& A, hipStream_t st) {
+  const Grid gr = grid_for((A.n_cells + 255) / 256);
+  hipLaunchKernelGGL(k_backward_lane<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
+template <int N>
+static int launch_backward_wave(const BackArgs& A, hipStream_t st) {
+  const Grid gr = grid_for((A.n_cells + 3) / 4);
+  hipLaunchKernelGGL(k_backward_wave<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
+static BwdFn wave_bwd(int N) {
+  static const BwdFn tab[16] = {
+      launch_backward_wave<1>,  launch_backward_wave<2>,  launch_backward_wave<3>,
+      launch_backward_wave<4>,  launch_backward_wave<5>,  launch_backward_wave<6>,
+      launch_backward_wave<7>,  launch_backward_wave<8>,  launch_backward_wave<9>,
+      launch_backward_wave<10>, launch_backward_wave<11>, launch_backward_wave<12>,
+      launch_backward_wave<13>, launch_backward_wave<14>, launch_backward_wave<15>,
+      launch_backward_wave<16>};
+  return tab[N - 1];
+}
+
+static BwdFn lane_bwd(int N) {
+  static const BwdFn tab[kLaneMaxN] = {
+      launch_backward_lane<1>, launch_backward_lane<2>, launch_backward_lane<3>,
+      launch_backward_lane<4>, launch_backward_lane<5>, launch_backward_lane<6>,
+      launch_backward_lane<7>, launch_backward_lane<8>};
+  return tab[N - 1];
+}
 
 static FwdFn wave_fwd(int N) {
   static const FwdFn tab[16] = {
@@ -136,9 +171,25 @@ static int g_default_map[16] = {
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
 static int g_map_override[16] = {0};
 
+// Default mapping of the adjoint.  It keeps three N x N matrices per lane;
+// at N = 8 the lane kernel spills, yet measured on MI355X it still beats the
+// MFMA kernel (whose 16 x 16 tile is 7/8 padding at N = 8).
+static int g_default_map_bwd[16] = {
+    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
+    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
+    DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
+    DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
+
 static int mapping_for(int N) {
   const int o = g_map_override[N - 1];
   int m = o ? o : g_default_map[N - 1];
+  if (m == DRAG_MAP_LANE && N > kLaneMaxN) m = DRAG_MAP_WAVE;
+  return m;
+}
+
+static int mapping_for_bwd(int N) {
+  const int o = g_map_override[N - 1];
+  int m = o ? o : g_default_map_bwd[N - 1];
   if (m == DRAG_MAP_LANE && N > kLaneMaxN) m = DRAG_MAP_WAVE;
   return m;
 }
@@ -243,12 +294,29 @@ int drag_expm_apply(const drag_desc* d, const double* rho_g, const double* rho_d
 
 int drag_expm_apply_backward(const drag_desc* d, const double* rho_g, const double* rho_d,
                              const double* t_stop, const double* v_in, const double* w,
-                             double*, double*, double*, double*, double*, drag_stream_t) {
+                             double* v_out, double* g_v, double* g_logt, double* g_t,
+                             double* g_rho_d, double* g_rho_g, drag_stream_t stream) {
   int rc = check_desc(d);
   if (rc) return rc;
   if (d->n_cells == 0) return DRAG_OK;
   if (!rho_g || !rho_d || !t_stop || !v_in || !w) return DRAG_ERR_NULL_POINTER;
-  return DRAG_ERR_PLAN;
+  const int64_t C = d->n_cells, ld = d->ld, N = d->n_species, D = d->n_dim;
+  const int64_t nv = D * (N + 1);
+  const Range in[5] = {span(rho_g, 1, ld, C), span(rho_d, N, ld, C), span(t_stop, N, ld, C),
+                       span(v_in, nv, ld, C), span(w, nv, ld, C)};
+  const Range out[6] = {span(v_out, nv, ld, C), span(g_v, nv, ld, C), span(g_logt, N, ld, C),
+                        span(g_t, N, ld, C), span(g_rho_d, N, ld, C), span(g_rho_g, 1, ld, C)};
+  for (int x = 0; x < 6; ++x) {
+    for (const Range& i : in)
+      if (overlap(out[x], i)) return DRAG_ERR_ALIAS;
+    for (int y = x + 1; y < 6; ++y)
+      if (overlap(out[x], out[y])) return DRAG_ERR_ALIAS;
+  }
+  BackArgs B{rho_g, rho_d, t_stop, v_in, w, v_out, g_v, g_logt, g_t, g_rho_d, g_rho_g,
+             C,     ld,    d->dt,  (int)D, d->k_max, d->option};
+  const int map = mapping_for_bwd((int)N);
+  return map == DRAG_MAP_LANE ? lane_bwd((int)N)(B, (hipStream_t)stream)
+                              : wave_bwd((int)N)(B, (hipStream_t)stream);
 }
 
 int drag_plan_batched(const drag_batch_desc*, drag_plan** out) {

@@ -113,10 +113,12 @@ def build(rho_g, rho_d, t_stop, dt, k_max=9, option=2, stream=None):
 
 
 def expm_apply_backward(rho_g, rho_d, t_stop, v, grad_out, dt, k_max=9, option=2,
-                        want_v_out=True, want_grad_rho_g=True, stream=None):
+                        want_v_out=True, want_grad_rho_g=True, want_grad_t=False,
+                        stream=None):
     """Fused forward + adjoint (drag_expm_apply_backward).
 
-    Returns (v_out or None, grad_v, grad_log_t, grad_rho_d, grad_rho_g or None).
+    Returns (v_out or None, grad_v, grad_log_t, grad_rho_d, grad_rho_g or None),
+    plus grad_t_stop as a sixth item when ``want_grad_t``.
     """
     C, N, D, ld = _shapes(rho_g, rho_d, t_stop, v)
     _require(grad_out, "grad_out")
@@ -130,11 +132,14 @@ def expm_apply_backward(rho_g, rho_d, t_stop, v, grad_out, dt, k_max=9, option=2
     g_logt = torch.empty((N, C), dtype=torch.float64, device=dev)
     g_rho = torch.empty((N, C), dtype=torch.float64, device=dev)
     g_rho_g = torch.empty(C, dtype=torch.float64, device=dev) if want_grad_rho_g else None
+    g_t = torch.empty((N, C), dtype=torch.float64, device=dev) if want_grad_t else None
     desc = _lib.make_desc(C, N, D, C, dt, k_max, option)
     _lib.check(_lib.lib().drag_expm_apply_backward(
         ctypes.byref(desc), _ptr(rho_g), _ptr(rho_d), _ptr(t_stop), _ptr(v), _ptr(grad_out),
-        _ptr(v_out), _ptr(g_v), _ptr(g_logt), _ptr(g_rho), _ptr(g_rho_g),
+        _ptr(v_out), _ptr(g_v), _ptr(g_logt), _ptr(g_t), _ptr(g_rho), _ptr(g_rho_g),
         _stream_ptr(stream)), "drag_expm_apply_backward")
+    if want_grad_t:
+        return v_out, g_v, g_logt, g_rho, g_rho_g, g_t
     return v_out, g_v, g_logt, g_rho, g_rho_g
 
 
@@ -166,14 +171,12 @@ class DragExpm(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         rho_g, rho_d, t_stop, v = ctx.saved_tensors
-        _, g_v, g_logt, g_rho, g_rho_g = expm_apply_backward(
+        _, g_v, g_logt, g_rho, g_rho_g, g_t = expm_apply_backward(
             rho_g, rho_d, t_stop, v, grad_out.contiguous(), ctx.dt, ctx.k_max, ctx.option,
-            want_v_out=False)
-        # d/dt_i = d/dlog t_i / t_i
-        g_t = g_logt / t_stop if ctx.needs_input_grad[2] else None
+            want_v_out=False, want_grad_t=True)
         return (g_rho_g if ctx.needs_input_grad[0] else None,
                 g_rho if ctx.needs_input_grad[1] else None,
-                g_t,
+                g_t if ctx.needs_input_grad[2] else None,
                 g_v if ctx.needs_input_grad[3] else None,
                 None, None, None)
 

@@ -84,7 +84,7 @@ def test_argument_errors_return_before_launch(L):
 
 def test_backward_argument_errors(L):
     d = _lib.make_desc(10, 4, 3, 10, 1.0)
-    nul = [None] * 11
+    nul = [None] * 12
     assert L.drag_expm_apply_backward(None, *nul) == _lib.ERR_NULL_DESC
     bad = _lib.make_desc(10, 20, 3, 10, 1.0)
     assert L.drag_expm_apply_backward(ctypes.byref(bad), *nul) == _lib.ERR_N_SPECIES
