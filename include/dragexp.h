@@ -173,6 +173,14 @@ int drag_plan_offsets(const drag_plan *plan, int64_t *field_offset,
 int drag_expm_apply_batched(drag_plan *plan, const double *fields,
                             const double *v_in, double *v_out,
                             drag_stream_t stream);
+/* Time every launch configuration of the plan on the caller's data (each
+ * run computes the full, valid result into v_out, then synchronises
+ * `stream`), keep the fastest, and report its lane-mapping bound: blocks
+ * with N_b <= *lane_max_out run one cell per lane, the others one cell per
+ * wavefront on FP64 MFMA.  The next drag_expm_apply_batched re-captures. */
+int drag_plan_autotune(drag_plan *plan, const double *fields,
+                       const double *v_in, double *v_out,
+                       drag_stream_t stream, int32_t *lane_max_out);
 int drag_plan_destroy(drag_plan *plan);
 
 /* ---- status and introspection -------------------------------------------- */

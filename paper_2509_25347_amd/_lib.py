@@ -53,7 +53,7 @@ MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 EXPORTS = [
     "drag_desc_init", "drag_build", "drag_expm_apply", "drag_expm_apply_backward",
     "drag_plan_batched", "drag_plan_offsets", "drag_expm_apply_batched",
-    "drag_plan_destroy", "drag_get_status", "drag_clear_status", "drag_status_string",
+    "drag_plan_autotune", "drag_plan_destroy", "drag_get_status", "drag_clear_status", "drag_status_string",
     "drag_table_row", "drag_select", "drag_set_mapping", "drag_get_mapping",
 ]
 
@@ -128,6 +128,8 @@ def lib():
     L.drag_plan_offsets.restype = ctypes.c_int
     L.drag_expm_apply_batched.argtypes = [vp, vp, vp, vp, vp]
     L.drag_expm_apply_batched.restype = ctypes.c_int
+    L.drag_plan_autotune.argtypes = [vp, vp, vp, vp, vp, P(i32)]
+    L.drag_plan_autotune.restype = ctypes.c_int
     L.drag_plan_destroy.argtypes = [vp]
     L.drag_plan_destroy.restype = ctypes.c_int
     L.drag_get_status.argtypes = [vp, P(i32)]

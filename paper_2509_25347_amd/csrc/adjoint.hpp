@@ -283,8 +283,8 @@ __global__ void __launch_bounds__(256) k_backward_wave(BackArgs A, int xcd_block
   const int D = A.n_dim;
   const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
 
-  WaveCell<N> Wc;
-  wave_setup<N>(Wc, A.rho_g, A.rho_d, A.t_stop, ld, cell, A.dt, A.k_max, A.option, j);
+  WaveCell Wc;
+  wave_setup(Wc, N, A.rho_g, A.rho_d, A.t_stop, ld, cell, A.dt, A.k_max, A.option, j);
 
   // velocity data in the component-species layout: lane (g = component c,
   // j = species) holds the cell's values of component c for species j

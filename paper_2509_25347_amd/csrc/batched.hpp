@@ -1,0 +1,100 @@
+// batched.hpp -- AMR-style blocks with uneven species counts N_b in [1, 16],
+// all updated by one hipGraph launch.
+//
+// Blocks are split by mapping.  Blocks with N_b > LMAX go to one persistent
+// MFMA grid (one cell per wavefront, N taken at run time, so a single code
+// path serves N = LMAX+1..16): the plan cuts them into work items of a few
+// cells, and every wavefront of the persistent grid takes the next item from
+// a device counter with one atomic add until the queue is empty, so blocks
+// of uneven cost balance themselves.  Blocks with N_b <= LMAX run one cell
+// per lane in one grid per N (one 64-cell item per wavefront), each compiled
+// with exactly the registers its N needs.  The plan captures all of them
+// into one graph whose lane and MFMA branches are independent, so they can
+// overlap.  Every item runs the same per-cell device code as the plain per-N
+// launches: a block's result is bit-identical to drag_expm_apply on that
+// block with the same mapping.
+//
+// LMAX is the tuned knob (drag_plan_autotune): the lane mapping is several
+// times faster per cell for small N, but its register demand grows as N^2.
+#pragma once
+
+#include "common.hpp"
+#include "lane.hpp"
+#include "wave.hpp"
+
+namespace dragexp {
+
+struct BatchItem {
+  int32_t block;  // block index
+  int32_t n;      // species count of the block
+  int32_t first;  // first cell of the item within the block
+  int32_t count;  // cells in the item; lane items hold at most 64
+};
+
+struct BatchArgs {
+  const BatchItem* items;
+  const int64_t* field_off;  // element offset of each block's field slab
+  const int64_t* v_off;      // element offset of each block's velocity slab
+  const double* fields;
+  const double* v_in;
+  double* v_out;
+  unsigned int* counter;     // MFMA queue head (persistent grid only)
+  int n_items;
+  int block_cells;
+  int n_dim;
+  int k_max;
+  int option;
+  double dt;
+};
+
+__global__ void k_batch_reset(unsigned int* counter) { *counter = 0u; }
+
+__device__ __forceinline__ CellArgs block_args(const BatchArgs& B, const BatchItem& it) {
+  const int bc = B.block_cells;
+  CellArgs A;
+  A.rho_g = B.fields + B.field_off[it.block];
+  A.rho_d = A.rho_g + bc;
+  A.t_stop = A.rho_d + (int64_t)it.n * bc;
+  A.v_in = B.v_in + B.v_off[it.block];
+  A.v_out = B.v_out + B.v_off[it.block];
+  A.n_cells = bc;
+  A.ld = bc;
+  A.dt = B.dt;
+  A.n_dim = B.n_dim;
+  A.k_max = B.k_max;
+  A.option = B.option;
+  return A;
+}
+
+// Persistent MFMA grid over the queue of wave items.
+__global__ void __launch_bounds__(256) k_batched_wave(BatchArgs B) {
+  __shared__ double lds[4 * 2 * kStageDoubles];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* bufX = lds + (2 * w) * kStageDoubles;
+  double* bufY = bufX + kStageDoubles;
+  for (;;) {
+    int idx = 0;
+    if (lane == 0) idx = (int)atomicAdd(B.counter, 1u);
+    idx = __shfl(idx, 0, 64);
+    if (idx >= B.n_items) break;  // uniform: every wavefront leaves once the queue is empty
+    const BatchItem it = B.items[idx];
+    const CellArgs A = block_args(B, it);
+    for (int k = 0; k < it.count; ++k)
+      wave_forward_cell(A, it.n, (int64_t)it.first + k, lane, bufX, bufY);
+  }
+}
+
+// One 64-cell lane item per wavefront, all items of one species count N.
+template <int N>
+__global__ void __launch_bounds__(256) k_batched_lane(BatchArgs B) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + w;
+  if (idx >= B.n_items) return;  // uniform over the wavefront
+  const BatchItem it = B.items[idx];
+  const CellArgs A = block_args(B, it);
+  const bool active = lane < it.count;
+  const int64_t c = (int64_t)it.first + lane;
+  lane_forward_cell<N>(A, c, active ? c : it.first, active);
+}
+
+}  // namespace dragexp

@@ -9,11 +9,15 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "../../include/dragexp.h"
 #include "common.hpp"
 #include "lane.hpp"
 #include "wave.hpp"
 #include "adjoint.hpp"
+#include "batched.hpp"
 
 namespace dragexp {
 
@@ -226,6 +230,227 @@ static bool overlap(Range a, Range b) {
   return a.lo < b.hi && b.lo < a.hi;
 }
 
+
+// ---- batched plans ----------------------------------------------------------------
+constexpr int kBatchVariants = 5;
+constexpr int kBatchLmax[kBatchVariants] = {4, 5, 6, 7, 8};
+constexpr int kWaveItemCells = 8;
+
+struct BatchVariant {
+  int lmax = 6;
+  BatchItem* d_wave = nullptr;  // MFMA queue (blocks with N > lmax)
+  int n_wave = 0;
+  BatchItem* d_lane[kLaneMaxN + 1] = {};  // 64-cell lane items per N <= lmax
+  int n_lane[kLaneMaxN + 1] = {};
+};
+
+template <int N>
+static void launch_batched_lane(const BatchArgs& B, hipStream_t st) {
+  hipLaunchKernelGGL(k_batched_lane<N>, dim3((B.n_items + 3) / 4), dim3(256), 0, st, B);
+}
+
+static void batched_lane(int N, const BatchArgs& B, hipStream_t st) {
+  switch (N) {
+    case 1: launch_batched_lane<1>(B, st); break;
+    case 2: launch_batched_lane<2>(B, st); break;
+    case 3: launch_batched_lane<3>(B, st); break;
+    case 4: launch_batched_lane<4>(B, st); break;
+    case 5: launch_batched_lane<5>(B, st); break;
+    case 6: launch_batched_lane<6>(B, st); break;
+    case 7: launch_batched_lane<7>(B, st); break;
+    default: launch_batched_lane<8>(B, st); break;
+  }
+}
+
+}  // namespace dragexp
+
+struct drag_plan {
+  int device = 0;
+  int n_blocks = 0, block_cells = 0, n_dim = 0, k_max = 9, option = 2;
+  double dt = 0.0;
+  std::vector<int32_t> n_species;
+  std::vector<int64_t> field_off, v_off;
+  int64_t fields_total = 0, v_total = 0;
+  int lmax = 6;
+  dragexp::BatchVariant var[dragexp::kBatchVariants];
+  int wave_grid = 0;
+  int64_t* d_field_off = nullptr;
+  int64_t* d_v_off = nullptr;
+  unsigned int* d_counter = nullptr;
+  hipStream_t cap_stream = nullptr, side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const double* g_fields = nullptr;
+  const double* g_vin = nullptr;
+  double* g_vout = nullptr;
+  int g_lmax = 0;
+};
+
+namespace dragexp {
+
+static void plan_drop_graph(drag_plan* P) {
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->exec = nullptr;
+  P->graph = nullptr;
+  P->g_fields = P->g_vin = nullptr;
+  P->g_vout = nullptr;
+  P->g_lmax = 0;
+}
+
+static void plan_free(drag_plan* P) {
+  plan_drop_graph(P);
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
+  for (BatchVariant& V : P->var) {
+    if (V.d_wave) (void)hipFree(V.d_wave);
+    for (BatchItem* p : V.d_lane)
+      if (p) (void)hipFree(p);
+  }
+  if (P->d_field_off) (void)hipFree(P->d_field_off);
+  if (P->d_v_off) (void)hipFree(P->d_v_off);
+  if (P->d_counter) (void)hipFree(P->d_counter);
+  delete P;
+}
+
+static int upload(BatchItem** dst, const std::vector<BatchItem>& host) {
+  if (host.empty()) return DRAG_OK;
+  if (hipMalloc(dst, sizeof(BatchItem) * host.size()) != hipSuccess) return DRAG_ERR_HIP;
+  if (hipMemcpy(*dst, host.data(), sizeof(BatchItem) * host.size(), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return DRAG_ERR_HIP;
+  return DRAG_OK;
+}
+
+static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
+  if (hipGetDevice(&P->device) != hipSuccess) return DRAG_ERR_HIP;
+  P->n_blocks = bd->n_blocks;
+  P->block_cells = bd->block_cells;
+  P->n_dim = bd->n_dim;
+  P->k_max = bd->k_max;
+  P->option = bd->option;
+  P->dt = bd->dt;
+  P->n_species.assign(bd->n_species, bd->n_species + bd->n_blocks);
+  const int64_t bc = bd->block_cells, D = bd->n_dim;
+  P->field_off.resize(P->n_blocks);
+  P->v_off.resize(P->n_blocks);
+  int64_t fo = 0, vo = 0;
+  for (int b = 0; b < P->n_blocks; ++b) {
+    const int64_t n = P->n_species[b];
+    P->field_off[b] = fo;
+    P->v_off[b] = vo;
+    fo += bc * (1 + 2 * n);
+    vo += bc * D * (n + 1);
+  }
+  P->fields_total = fo;
+  P->v_total = vo;
+  for (int v = 0; v < kBatchVariants; ++v) {
+    BatchVariant& V = P->var[v];
+    V.lmax = kBatchLmax[v];
+    std::vector<BatchItem> wave;
+    std::vector<BatchItem> lane[kLaneMaxN + 1];
+    for (int b = 0; b < P->n_blocks; ++b) {
+      const int n = P->n_species[b];
+      const bool is_lane = n <= V.lmax;
+      const int step = is_lane ? 64 : kWaveItemCells;
+      for (int first = 0; first < P->block_cells; first += step) {
+        const BatchItem it{b, n, first, std::min(step, P->block_cells - first)};
+        if (is_lane) lane[n].push_back(it);
+        else wave.push_back(it);
+      }
+    }
+    V.n_wave = (int)wave.size();
+    int rc = upload(&V.d_wave, wave);
+    for (int n = 1; n <= kLaneMaxN && !rc; ++n) {
+      V.n_lane[n] = (int)lane[n].size();
+      rc = upload(&V.d_lane[n], lane[n]);
+    }
+    if (rc) return rc;
+  }
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched_wave, 256, 0) != hipSuccess)
+    return DRAG_ERR_HIP;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess)
+    return DRAG_ERR_HIP;
+  P->wave_grid = (per_cu < 1 ? 1 : per_cu) * cus;
+  if (hipMalloc(&P->d_field_off, sizeof(int64_t) * P->n_blocks) != hipSuccess) return DRAG_ERR_HIP;
+  if (hipMalloc(&P->d_v_off, sizeof(int64_t) * P->n_blocks) != hipSuccess) return DRAG_ERR_HIP;
+  if (hipMalloc(&P->d_counter, sizeof(unsigned int)) != hipSuccess) return DRAG_ERR_HIP;
+  if (hipMemcpy(P->d_field_off, P->field_off.data(), sizeof(int64_t) * P->n_blocks,
+                hipMemcpyHostToDevice) != hipSuccess)
+    return DRAG_ERR_HIP;
+  if (hipMemcpy(P->d_v_off, P->v_off.data(), sizeof(int64_t) * P->n_blocks,
+                hipMemcpyHostToDevice) != hipSuccess)
+    return DRAG_ERR_HIP;
+  if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return DRAG_ERR_HIP;
+  if (hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking) != hipSuccess)
+    return DRAG_ERR_HIP;
+  if (hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess)
+    return DRAG_ERR_HIP;
+  if (hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess)
+    return DRAG_ERR_HIP;
+  return DRAG_OK;
+}
+
+// Enqueue one batched update (variant lmax) on `main`, the lane grids on
+// `side` between a fork and a join: captured, this is the plan's graph.
+static int plan_enqueue(drag_plan* P, int lmax, const double* fields, const double* v_in,
+                        double* v_out, hipStream_t main, hipStream_t side) {
+  int v = 0;
+  while (v + 1 < kBatchVariants && kBatchLmax[v] != lmax) ++v;
+  const BatchVariant& V = P->var[v];
+  BatchArgs B{nullptr, P->d_field_off, P->d_v_off, fields, v_in, v_out, P->d_counter,
+              0,       P->block_cells, P->n_dim, P->k_max, P->option, P->dt};
+  if (hipEventRecord(P->ev_fork, main) != hipSuccess) return DRAG_ERR_HIP;
+  if (hipStreamWaitEvent(side, P->ev_fork, 0) != hipSuccess) return DRAG_ERR_HIP;
+  for (int n = 1; n <= kLaneMaxN; ++n) {
+    if (V.n_lane[n] == 0) continue;
+    BatchArgs L = B;
+    L.items = V.d_lane[n];
+    L.n_items = V.n_lane[n];
+    batched_lane(n, L, side);
+  }
+  if (hipEventRecord(P->ev_join, side) != hipSuccess) return DRAG_ERR_HIP;
+  if (V.n_wave > 0) {
+    BatchArgs W = B;
+    W.items = V.d_wave;
+    W.n_items = V.n_wave;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, main, P->d_counter);
+    hipLaunchKernelGGL(k_batched_wave, dim3(P->wave_grid), dim3(256), 0, main, W);
+  }
+  if (hipStreamWaitEvent(main, P->ev_join, 0) != hipSuccess) return DRAG_ERR_HIP;
+  return hip_status(hipGetLastError());
+}
+
+// Capture the update for these pointers and this lmax into the plan's graph.
+static int plan_capture(drag_plan* P, int lmax, const double* fields, const double* v_in,
+                        double* v_out) {
+  plan_drop_graph(P);
+  if (hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return DRAG_ERR_HIP;
+  const int rc = plan_enqueue(P, lmax, fields, v_in, v_out, P->cap_stream, P->side_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+  if (rc || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return DRAG_ERR_HIP;
+  }
+  P->graph = g;
+  if (hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess) {
+    P->exec = nullptr;
+    return DRAG_ERR_HIP;
+  }
+  P->g_fields = fields;
+  P->g_vin = v_in;
+  P->g_vout = v_out;
+  P->g_lmax = lmax;
+  return DRAG_OK;
+}
+
 }  // namespace dragexp
 
 using namespace dragexp;
@@ -319,17 +544,105 @@ int drag_expm_apply_backward(const drag_desc* d, const double* rho_g, const doub
                               : wave_bwd((int)N)(B, (hipStream_t)stream);
 }
 
-int drag_plan_batched(const drag_batch_desc*, drag_plan** out) {
-  if (out) *out = nullptr;
-  return DRAG_ERR_PLAN;
+int drag_plan_batched(const drag_batch_desc* bd, drag_plan** out) {
+  if (!out) return DRAG_ERR_NULL_POINTER;
+  *out = nullptr;
+  if (!bd) return DRAG_ERR_NULL_DESC;
+  if (bd->n_blocks < 1 || bd->block_cells < 1 || !bd->n_species) return DRAG_ERR_PLAN;
+  if (bd->n_dim < 1 || bd->n_dim > 3) return DRAG_ERR_N_DIM;
+  if (!(bd->dt >= 0.0) || !isfinite(bd->dt)) return DRAG_ERR_DT;
+  if (bd->k_max < 1 || bd->k_max > 9) return DRAG_ERR_K_MAX;
+  if (bd->option < 0 || bd->option > 2) return DRAG_ERR_OPTION;
+  for (int b = 0; b < bd->n_blocks; ++b)
+    if (bd->n_species[b] < 1 || bd->n_species[b] > kMaxSpecies) return DRAG_ERR_N_SPECIES;
+  drag_plan* P = new drag_plan();
+  int rc = plan_init(P, bd);
+  if (rc) {
+    plan_free(P);
+    return rc;
+  }
+  *out = P;
+  return DRAG_OK;
 }
-int drag_plan_offsets(const drag_plan*, int64_t*, int64_t*, int64_t*, int64_t*) {
-  return DRAG_ERR_PLAN;
+
+int drag_plan_offsets(const drag_plan* P, int64_t* field_offset, int64_t* v_offset,
+                      int64_t* fields_total, int64_t* v_total) {
+  if (!P) return DRAG_ERR_PLAN;
+  if (field_offset)
+    memcpy(field_offset, P->field_off.data(), sizeof(int64_t) * P->field_off.size());
+  if (v_offset) memcpy(v_offset, P->v_off.data(), sizeof(int64_t) * P->v_off.size());
+  if (fields_total) *fields_total = P->fields_total;
+  if (v_total) *v_total = P->v_total;
+  return DRAG_OK;
 }
-int drag_expm_apply_batched(drag_plan*, const double*, const double*, double*, drag_stream_t) {
-  return DRAG_ERR_PLAN;
+
+int drag_expm_apply_batched(drag_plan* P, const double* fields, const double* v_in,
+                            double* v_out, drag_stream_t stream) {
+  if (!P) return DRAG_ERR_PLAN;
+  if (!fields || !v_in || !v_out) return DRAG_ERR_NULL_POINTER;
+  const Range rf{(uintptr_t)fields, (uintptr_t)(fields + P->fields_total)};
+  const Range ri{(uintptr_t)v_in, (uintptr_t)(v_in + P->v_total)};
+  const Range ro{(uintptr_t)v_out, (uintptr_t)(v_out + P->v_total)};
+  if (overlap(ro, rf)) return DRAG_ERR_ALIAS;
+  if ((const double*)v_out != v_in && overlap(ro, ri)) return DRAG_ERR_ALIAS;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != P->device) return DRAG_ERR_PLAN;
+  if (!P->exec || P->g_fields != fields || P->g_vin != v_in || P->g_vout != v_out ||
+      P->g_lmax != P->lmax) {
+    const int rc = plan_capture(P, P->lmax, fields, v_in, v_out);
+    if (rc) return rc;
+  }
+  return hip_status(hipGraphLaunch(P->exec, (hipStream_t)stream));
 }
-int drag_plan_destroy(drag_plan*) { return DRAG_OK; }
+
+int drag_plan_autotune(drag_plan* P, const double* fields, const double* v_in, double* v_out,
+                       drag_stream_t stream, int32_t* lane_max_out) {
+  if (!P) return DRAG_ERR_PLAN;
+  if (!fields || !v_in || !v_out) return DRAG_ERR_NULL_POINTER;
+  const Range rf{(uintptr_t)fields, (uintptr_t)(fields + P->fields_total)};
+  const Range ri{(uintptr_t)v_in, (uintptr_t)(v_in + P->v_total)};
+  const Range ro{(uintptr_t)v_out, (uintptr_t)(v_out + P->v_total)};
+  if (overlap(ro, rf) || overlap(ro, ri)) return DRAG_ERR_ALIAS;  // runs repeat: no in-place
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return DRAG_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DRAG_ERR_HIP;
+  }
+  float best_ms = 0.0f;
+  int best = P->lmax, rc = DRAG_OK;
+  for (int v = 0; v < kBatchVariants && rc == DRAG_OK; ++v) {
+    rc = plan_capture(P, kBatchLmax[v], fields, v_in, v_out);
+    float ms = 0.0f;
+    for (int rep = 0; rep < 3 && rc == DRAG_OK; ++rep) {  // rep 0 warms up
+      rc = hip_status(hipEventRecord(e0, st));
+      if (!rc) rc = hip_status(hipGraphLaunch(P->exec, st));
+      if (!rc) rc = hip_status(hipEventRecord(e1, st));
+      if (!rc) rc = hip_status(hipEventSynchronize(e1));
+      float t = 0.0f;
+      if (!rc) rc = hip_status(hipEventElapsedTime(&t, e0, e1));
+      if (rep == 1 || (rep > 1 && t < ms)) ms = t;
+    }
+    if (!rc && (v == 0 || ms < best_ms)) {
+      best_ms = ms;
+      best = kBatchLmax[v];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan_drop_graph(P);
+  if (rc) return rc;
+  P->lmax = best;
+  if (lane_max_out) *lane_max_out = best;
+  return DRAG_OK;
+}
+
+int drag_plan_destroy(drag_plan* P) {
+  if (!P) return DRAG_OK;
+  plan_free(P);
+  return DRAG_OK;
+}
 
 int drag_get_status(drag_stream_t stream, int32_t* host_status) {
   if (!host_status) return DRAG_ERR_NULL_POINTER;

@@ -148,16 +148,13 @@ __device__ __forceinline__ void lane_expm(double (&Z)[N][N], const LaneCell<N>& 
   }
 }
 
+// The forward update of cell c by one lane.  Every lane of the wavefront
+// must call it together (the Taylor and squaring loops run to the
+// wavefront's largest m and s); an inactive lane passes the index of any
+// valid cell as cc, computes on it and stores nothing.
 template <int N>
-__global__ void __launch_bounds__(256) k_forward_lane(CellArgs A, int xcd_blocks) {
-  // XCD-aware order: consecutive workgroup ids go to different XCDs, so
-  // hand each XCD a contiguous range of cells.
-  const int bid = blockIdx.x;
-  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
-  const int64_t c = logical * 256 + threadIdx.x;
-  const bool active = c < A.n_cells;
-  const int64_t cc = active ? c : 0;  // inactive lanes shadow cell 0, store nothing
-
+__device__ __forceinline__ void lane_forward_cell(const CellArgs& A, int64_t c, int64_t cc,
+                                                  bool active) {
   LaneCell<N> C;
   lane_setup<N>(C, A.rho_g, A.rho_d, A.t_stop, A.ld, cc, A.dt, A.k_max, A.option);
   double Z[N][N];
@@ -197,6 +194,17 @@ __global__ void __launch_bounds__(256) k_forward_lane(CellArgs A, int xcd_blocks
     }
   }
   if (C.bad && active) atomicOr(&g_status_word, C.bad);
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_forward_lane(CellArgs A, int xcd_blocks) {
+  // XCD-aware order: consecutive workgroup ids go to different XCDs, so
+  // hand each XCD a contiguous range of cells.
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int64_t c = logical * 256 + threadIdx.x;
+  const bool active = c < A.n_cells;
+  lane_forward_cell<N>(A, c, active ? c : 0, active);
 }
 
 }  // namespace dragexp

@@ -68,7 +68,9 @@ __device__ __forceinline__ v4d mma16(const double (&A)[4], const double (&B)[4],
 // species j.  Every lane computes the norm's sums in ascending species
 // order from broadcast values, so ||A||_1 is the same bits as the
 // definition.  Returns the bad-input bits (uniform over the wavefront).
-template <int N>
+// N is a run-time argument throughout the MFMA path (it only bounds loops
+// and masks the padded rows and columns of the 16 x 16 tile); the per-N
+// kernels pass a constant and the compiler folds it.
 struct WaveCell {
   double aj, ej, pj;  // species j = lane % 16 (0 for j >= N)
   double sigma, nrm;
@@ -76,8 +78,7 @@ struct WaveCell {
   Kms kms;
 };
 
-template <int N>
-__device__ __forceinline__ void wave_setup(WaveCell<N>& W, const double* rho_g,
+__device__ __forceinline__ void wave_setup(WaveCell& W, const int N, const double* rho_g,
                                            const double* rho_d, const double* t_stop,
                                            int64_t ld, int64_t cell, double dt, int K,
                                            int option, int j) {
@@ -115,9 +116,8 @@ __device__ __forceinline__ void wave_setup(WaveCell<N>& W, const double* rho_g,
 }
 
 // Z = T_m(2^-s At)^(2^s) - I in the D layout (rows 4v+g, column j).
-template <int N>
-__device__ __forceinline__ v4d wave_expm(const WaveCell<N>& W, int g, int j, double* bufX,
-                                         double* bufY) {
+__device__ __forceinline__ v4d wave_expm(const WaveCell& W, const int N, int g, int j,
+                                         double* bufX, double* bufY) {
   const int s = W.kms.s;
   const int q = kTabQ[W.kms.k], r = kTabR[W.kms.k];
   const double bj = ldexp(W.aj, -s);
@@ -197,23 +197,17 @@ __device__ __forceinline__ v4d wave_expm(const WaveCell<N>& W, int g, int j, dou
   return Z;
 }
 
-template <int N>
-__global__ void __launch_bounds__(256) k_forward_wave(CellArgs A, int xcd_blocks) {
-  __shared__ double lds[4 * 2 * kStageDoubles];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// The forward update of one cell by a whole wavefront (lane = 0..63), with
+// two 16 x 17 LDS tiles private to the wavefront.
+__device__ __forceinline__ void wave_forward_cell(const CellArgs& A, const int N, int64_t cell,
+                                                  int lane, double* bufX, double* bufY) {
   const int g = lane >> 4, j = lane & 15;
-  const int bid = blockIdx.x;
-  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
-  const int64_t cell = logical * 4 + w;
-  if (cell >= A.n_cells) return;  // uniform over the wavefront
-  double* bufX = lds + (2 * w) * kStageDoubles;
-  double* bufY = bufX + kStageDoubles;
   const int64_t ld = A.ld;
   const int n1 = N + 1;
   const int D = A.n_dim;
 
-  WaveCell<N> W;
-  wave_setup<N>(W, A.rho_g, A.rho_d, A.t_stop, ld, cell, A.dt, A.k_max, A.option, j);
+  WaveCell W;
+  wave_setup(W, N, A.rho_g, A.rho_d, A.t_stop, ld, cell, A.dt, A.k_max, A.option, j);
 
   // velocities: lane (g, col = j < D) loads the relative velocities of rows
   // 4t + g as the B operand of the final product
@@ -240,7 +234,7 @@ __global__ void __launch_bounds__(256) k_forward_wave(CellArgs A, int xcd_blocks
     return;
   }
 
-  const v4d Z = wave_expm<N>(W, g, j, bufX, bufY);
+  const v4d Z = wave_expm(W, N, g, j, bufX, bufY);
 
   // u = Z dv for every component at once
   double Az[4];
@@ -269,6 +263,18 @@ __global__ void __launch_bounds__(256) k_forward_wave(CellArgs A, int xcd_blocks
     }
     if (g == 0) A.v_out[(int64_t)(j * n1) * ld + cell] = v0 + d0;
   }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_forward_wave(CellArgs A, int xcd_blocks) {
+  __shared__ double lds[4 * 2 * kStageDoubles];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int64_t cell = logical * 4 + w;
+  if (cell >= A.n_cells) return;  // uniform over the wavefront
+  double* bufX = lds + (2 * w) * kStageDoubles;
+  wave_forward_cell(A, N, cell, lane, bufX, bufX + kStageDoubles);
 }
 
 }  // namespace dragexp

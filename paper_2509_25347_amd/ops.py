@@ -184,3 +184,92 @@ class DragExpm(torch.autograd.Function):
 def drag_expm(rho_g, rho_d, t_stop, v, dt, k_max=9, option=2):
     """Differentiable v' = exp(dt K) v (see DragExpm)."""
     return DragExpm.apply(rho_g, rho_d, t_stop, v, dt, k_max, option)
+
+
+class BatchPlan:
+    """AMR-style blocks with uneven species counts in one graph launch
+    (drag_plan_batched / drag_expm_apply_batched).
+
+    Block b's fields live in one flat float64 buffer at ``field_offset[b]``:
+    rho_g [bc] | rho_d [N_b][bc] | t_stop [N_b][bc]; its velocities in a
+    second buffer at ``v_offset[b]``: v [D][N_b+1][bc].  ``pack`` lays out
+    host arrays that way (input preparation, outside the hot path).
+    """
+
+    def __init__(self, n_species, block_cells, n_dim, dt, k_max=9, option=2):
+        import numpy as np
+        L = _lib.lib()
+        self.n_species = [int(x) for x in n_species]
+        self.block_cells = int(block_cells)
+        self.n_dim = int(n_dim)
+        self.dt = float(dt)
+        nb = len(self.n_species)
+        self._arr = (ctypes.c_int32 * nb)(*self.n_species)
+        desc = _lib.DragBatchDesc(nb, self.block_cells, self.n_dim, int(k_max), int(option),
+                                  self.dt, ctypes.cast(self._arr, ctypes.POINTER(ctypes.c_int32)))
+        plan = ctypes.c_void_p()
+        _lib.check(L.drag_plan_batched(ctypes.byref(desc), ctypes.byref(plan)),
+                   "drag_plan_batched")
+        self._plan = plan
+        self.field_offset = np.zeros(nb, dtype=np.int64)
+        self.v_offset = np.zeros(nb, dtype=np.int64)
+        ft, vt = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(L.drag_plan_offsets(plan, self.field_offset.ctypes.data_as(ctypes.c_void_p),
+                                       self.v_offset.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.byref(ft), ctypes.byref(vt)), "drag_plan_offsets")
+        self.fields_total, self.v_total = ft.value, vt.value
+
+    def pack(self, blocks, device):
+        """Flat (fields, v) GPU buffers from per-block dicts of numpy arrays."""
+        import numpy as np
+        bc = self.block_cells
+        f = np.empty(self.fields_total)
+        v = np.empty(self.v_total)
+        for b, blk in enumerate(blocks):
+            n = self.n_species[b]
+            o = self.field_offset[b]
+            f[o:o + bc] = blk["rho_g"]
+            f[o + bc:o + bc + n * bc] = blk["rho_d"].ravel()
+            f[o + bc + n * bc:o + bc + 2 * n * bc] = blk["t_stop"].ravel()
+            ov = self.v_offset[b]
+            v[ov:ov + self.n_dim * (n + 1) * bc] = blk["v"].ravel()
+        return (torch.from_numpy(f).to(device), torch.from_numpy(v).to(device))
+
+    def block_view(self, v, b):
+        """The [D][N_b+1][bc] view of block b inside a flat velocity buffer."""
+        n = self.n_species[b]
+        o = int(self.v_offset[b])
+        return v[o:o + self.n_dim * (n + 1) * self.block_cells].view(
+            self.n_dim, n + 1, self.block_cells)
+
+    def apply(self, fields, v_in, v_out=None, stream=None):
+        for x, nm in ((fields, "fields"), (v_in, "v_in")):
+            _require(x, nm)
+        if v_out is None:
+            v_out = torch.empty_like(v_in)
+        _require(v_out, "v_out")
+        if fields.numel() < self.fields_total or v_in.numel() < self.v_total or \
+                v_out.numel() < self.v_total:
+            raise ValueError("buffers smaller than the plan's layout")
+        _lib.check(_lib.lib().drag_expm_apply_batched(self._plan, _ptr(fields), _ptr(v_in),
+                                                      _ptr(v_out), _stream_ptr(stream)),
+                   "drag_expm_apply_batched")
+        return v_out
+
+    def autotune(self, fields, v_in, v_out, stream=None) -> int:
+        lm = ctypes.c_int32()
+        _lib.check(_lib.lib().drag_plan_autotune(self._plan, _ptr(fields), _ptr(v_in),
+                                                 _ptr(v_out), _stream_ptr(stream),
+                                                 ctypes.byref(lm)), "drag_plan_autotune")
+        return lm.value
+
+    def close(self):
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            _lib.lib().drag_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

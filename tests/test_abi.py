@@ -110,6 +110,30 @@ def test_selection_matches_oracle_exactly(L, orc):
                 assert _lib.select(nrm, K, opt) == orc.select(nrm, K, opt), (nrm, K, opt)
 
 
+def test_batched_plan_argument_errors(L):
+    plan = ctypes.c_void_p()
+    assert L.drag_plan_batched(None, ctypes.byref(plan)) == _lib.ERR_NULL_DESC
+    ns = (ctypes.c_int32 * 3)(1, 5, 16)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    def d(**kw):
+        a = dict(n_blocks=3, block_cells=8, n_dim=3, k_max=9, option=2, dt=1.0)
+        a.update(kw)
+        return _lib.DragBatchDesc(a["n_blocks"], a["block_cells"], a["n_dim"], a["k_max"],
+                                  a["option"], a["dt"], ctypes.cast(ns, P32))
+    assert L.drag_plan_batched(ctypes.byref(d(n_blocks=0)), ctypes.byref(plan)) == _lib.ERR_PLAN
+    assert L.drag_plan_batched(ctypes.byref(d(n_dim=4)), ctypes.byref(plan)) == _lib.ERR_N_DIM
+    assert L.drag_plan_batched(ctypes.byref(d(dt=-1.0)), ctypes.byref(plan)) == _lib.ERR_DT
+    assert L.drag_plan_batched(ctypes.byref(d(k_max=0)), ctypes.byref(plan)) == _lib.ERR_K_MAX
+    assert L.drag_plan_batched(ctypes.byref(d(option=5)), ctypes.byref(plan)) == _lib.ERR_OPTION
+    bad = (ctypes.c_int32 * 3)(1, 0, 16)
+    dd = d()
+    dd.n_species = ctypes.cast(bad, P32)
+    assert L.drag_plan_batched(ctypes.byref(dd), ctypes.byref(plan)) == _lib.ERR_N_SPECIES
+    assert L.drag_expm_apply_batched(None, None, None, None, None) == _lib.ERR_PLAN
+    assert L.drag_plan_offsets(None, None, None, None, None) == _lib.ERR_PLAN
+    assert L.drag_plan_destroy(None) == _lib.OK
+
+
 def test_mapping_controls(L):
     for N in range(1, 17):
         assert _lib.get_mapping(N) in (_lib.MAP_LANE, _lib.MAP_WAVE)

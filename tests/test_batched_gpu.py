@@ -1,0 +1,156 @@
+"""GPU tests of the batched uneven-N launch (one hipGraph over AMR blocks).
+
+Each block's result must be bit-identical to the plain per-N launch on that
+block with the same mapping (the batched items run the same per-cell code),
+and within the parity bar of the oracle.  Graph replays are checked against
+the eager result with other GPU work between replays.
+"""
+import numpy as np
+import pytest
+
+from paper_2509_25347_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_25347_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ops(dev):
+    from paper_2509_25347_amd import ops as _ops
+    return _ops
+
+
+def plain_per_block(ops, batch, dev, lane_max):
+    """drag_expm_apply on every block with the batched plan's mapping."""
+    from paper_2509_25347_amd import _lib
+    outs = []
+    try:
+        for N in range(1, 17):
+            _lib.set_mapping(N, _lib.MAP_LANE if N <= lane_max else _lib.MAP_WAVE)
+        for blk in batch["blocks"]:
+            T = {k: torch.from_numpy(np.ascontiguousarray(blk[k])).to(dev)
+                 for k in ("rho_g", "rho_d", "t_stop", "v")}
+            outs.append(ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                       batch["dt"]).cpu().numpy())
+    finally:
+        for N in range(1, 17):
+            _lib.set_mapping(N, _lib.MAP_AUTO)
+    return outs
+
+
+def test_batched_matches_plain_and_oracle(ops, dev, orc):
+    batch = W.make_batched(n_blocks=48, block_cells=100, seed_cfg=41)
+    plan = ops.BatchPlan(batch["n_species"], 100, 3, batch["dt"])
+    fields, v = plan.pack(batch["blocks"], dev)
+    out = plan.apply(fields, v)
+    torch.cuda.synchronize()
+    ref = plain_per_block(ops, batch, dev, lane_max=6)
+    for b, blk in enumerate(batch["blocks"]):
+        got = plan.block_view(out, b).cpu().numpy()
+        assert np.array_equal(got, ref[b]), b
+        if b % 6 == 0:
+            o, kms, nrm, st = orc.apply_cells(blk["rho_g"], blk["rho_d"], blk["t_stop"], blk["v"],
+                                              batch["dt"])
+            scale = np.abs(blk["v"]).max(axis=1)
+            e = (np.abs(got - o).max(axis=1) / scale).max(axis=0)
+            assert (e <= np.maximum(4 * U * nrm, 1e-13)).all(), b
+    plan.close()
+
+
+def test_autotune_and_every_variant_result(ops, dev):
+    batch = W.make_batched(n_blocks=64, block_cells=70, seed_cfg=43)
+    plan = ops.BatchPlan(batch["n_species"], 70, 3, batch["dt"])
+    fields, v = plan.pack(batch["blocks"], dev)
+    out = torch.empty_like(v)
+    lm = plan.autotune(fields, v, out)
+    assert 4 <= lm <= 8
+    out2 = plan.apply(fields, v)
+    torch.cuda.synchronize()
+    ref = plain_per_block(ops, batch, dev, lane_max=lm)
+    for b in range(len(batch["blocks"])):
+        assert np.array_equal(plan.block_view(out2, b).cpu().numpy(), ref[b]), b
+    plan.close()
+
+
+def test_graph_replays_and_recapture(ops, dev):
+    batch = W.make_batched(n_blocks=40, block_cells=128, seed_cfg=45)
+    plan = ops.BatchPlan(batch["n_species"], 128, 3, batch["dt"])
+    fields, v = plan.pack(batch["blocks"], dev)
+    out = torch.empty_like(v)
+    first = plan.apply(fields, v, out).clone()
+    # other work on the same GPU between replays, then replay and compare
+    junk = torch.randn(1 << 20, dtype=torch.float64, device=dev)
+    d = W.make("n16_stiff_3d", 512)
+    T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
+    for rep in range(4):
+        junk = junk * 1.0001 + 1.0
+        ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], 1.0)
+        out.fill_(np.nan)
+        plan.apply(fields, v, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, first), rep
+    # new pointers: the plan re-captures
+    v2 = v.clone()
+    out2 = plan.apply(fields, v2)
+    assert torch.equal(out2, first)
+    # in place
+    plan.apply(fields, v2, v2)
+    assert torch.equal(v2, first)
+    plan.close()
+
+
+def test_batched_bad_cells_and_errors(ops, dev, orc):
+    from paper_2509_25347_amd import _lib
+    batch = W.make_batched(n_blocks=8, block_cells=64, seed_cfg=47)
+    batch["blocks"][2]["rho_g"] = batch["blocks"][2]["rho_g"].copy()
+    batch["blocks"][2]["rho_g"][5] = -1.0
+    plan = ops.BatchPlan(batch["n_species"], 64, 3, batch["dt"])
+    fields, v = plan.pack(batch["blocks"], dev)
+    ops.clear_status()
+    out = plan.apply(fields, v)
+    assert ops.get_status() == orc.BAD_DENSITY
+    assert torch.isnan(plan.block_view(out, 2)[..., 5]).all()
+    assert torch.isfinite(plan.block_view(out, 2)[..., :5]).all()
+    # an output that overlaps the fields buffer is rejected by the library
+    big = torch.empty(plan.fields_total + plan.v_total, dtype=torch.float64, device=dev)
+    big[: plan.fields_total] = fields
+    f2 = big[: plan.fields_total]
+    with pytest.raises(_lib.DragError):
+        plan.apply(f2, v, big[plan.fields_total - 8: plan.fields_total - 8 + plan.v_total])
+    with pytest.raises(_lib.DragError):
+        ops.BatchPlan([3, 17], 64, 3, 1.0)
+    plan.close()
+
+
+def test_full_size_batched_sampled(ops, dev, orc):
+    """4096 blocks of 8^3 cells, N_b ~ U{1..16}: sampled blocks against the
+    oracle, every block's momentum conserved."""
+    batch = W.make_batched()
+    plan = ops.BatchPlan(batch["n_species"], batch["block_cells"], 3, batch["dt"])
+    fields, v = plan.pack(batch["blocks"], dev)
+    out = plan.apply(fields, v)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for b in rng.choice(len(batch["blocks"]), 24, replace=False):
+        blk = batch["blocks"][b]
+        got = plan.block_view(out, b).cpu().numpy()
+        o, kms, nrm, st = orc.apply_cells(blk["rho_g"][:64], blk["rho_d"][:, :64],
+                                          blk["t_stop"][:, :64], blk["v"][..., :64], batch["dt"])
+        scale = np.abs(blk["v"][..., :64]).max(axis=1)
+        e = (np.abs(got[..., :64] - o).max(axis=1) / scale).max(axis=0)
+        assert (e <= np.maximum(4 * U * nrm, 1e-13)).all(), b
+        rho = np.concatenate([blk["rho_g"][None], blk["rho_d"]])
+        p0 = (rho[None] * blk["v"]).sum(axis=1)
+        p1 = (rho[None] * got).sum(axis=1)
+        assert (np.abs(p1 - p0) / (rho[None] * np.abs(blk["v"])).sum(axis=1)).max() <= 1e-12
+    plan.close()
