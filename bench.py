@@ -88,8 +88,13 @@ def main():
     ap.add_argument("--workload", default="n16_stiff_3d")
     ap.add_argument("--cells", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparisons", action="store_true",
+                    help="skip the fused-adjoint and batched comparisons against the plain forward")
     ap.add_argument("--extra", action="store_true",
-                    help="also time the other workloads and the fused adjoint")
+                    help="also time the other workloads, the fused adjoint and the batched launch")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (3 times), the "
+                         "reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -102,6 +107,15 @@ def main():
     _lib.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": src.numel() * 8,
+                          "copy_calibration_bytes_written": dst.numel() * 8}), flush=True)
+        return
 
     name = args.workload
     d = workloads.make(name, args.cells)
@@ -172,8 +186,11 @@ def main():
         "roofline": roof,
         "wall_s_timed": wall,
     }
+    if not args.no_comparisons:
+        res["fwd_bwd_vs_fwd"] = adjoint_measurement(torch, ops, workloads, dev)
+        res["batched_vs_plain"] = batched_measurement(torch, ops, workloads, dev)
     if args.extra:
-        res["extra"] = extra_measurements(torch, ops, workloads, dev, d, T, out, args)
+        res["extra"] = extra_measurements(torch, ops, workloads, dev)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(res), flush=True)
@@ -193,7 +210,53 @@ def _time(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def extra_measurements(torch, ops, workloads, dev, d, T, out, args):
+def adjoint_measurement(torch, ops, workloads, dev):
+    """Fused forward + adjoint against the plain forward, N = 8, 2^18 cells."""
+    dd = workloads.make("n8_adjoint_3d", with_weights=True)
+    TT = {k: torch.from_numpy(dd[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v", "w")}
+    oo = torch.empty_like(TT["v"])
+    tf = _time(torch, lambda: ops.expm_apply(TT["rho_g"], TT["rho_d"], TT["t_stop"], TT["v"],
+                                             dd["dt"], out=oo), 20, 3)
+    tb = _time(torch, lambda: ops.expm_apply_backward(TT["rho_g"], TT["rho_d"], TT["t_stop"],
+                                                      TT["v"], TT["w"], dd["dt"]), 10, 2)
+    return {"workload": "n8_adjoint_3d", "n_cells": int(dd["rho_g"].shape[0]),
+            "fwd_ms": tf, "fwd_bwd_ms": tb, "fwd_bwd_over_fwd": tb / tf}
+
+
+def batched_measurement(torch, ops, workloads, dev):
+    """The batched uneven-N graph against the plain per-N launches over the
+    same cells (blocks grouped by N into contiguous arrays)."""
+    import numpy as np
+    batch = workloads.make_batched()
+    plan = ops.BatchPlan(batch["n_species"], batch["block_cells"], 3, batch["dt"])
+    fields, v = plan.pack(batch["blocks"], dev)
+    out = torch.empty_like(v)
+    plan.autotune(fields, v, out)
+    lane_max, persistent = plan.config()
+    tb = _time(torch, lambda: plan.apply(fields, v, out), 10, 2)
+    groups = {}
+    for b, blk in enumerate(batch["blocks"]):
+        groups.setdefault(int(batch["n_species"][b]), []).append(blk)
+    per = []
+    for N, bl in sorted(groups.items()):
+        cat = {k: torch.from_numpy(np.ascontiguousarray(np.concatenate([x[k] for x in bl], -1))).to(dev)
+               for k in ("rho_g", "rho_d", "t_stop", "v")}
+        per.append((cat, torch.empty_like(cat["v"])))
+
+    def plain():
+        for cat, o in per:
+            ops.expm_apply(cat["rho_g"], cat["rho_d"], cat["t_stop"], cat["v"], batch["dt"], out=o)
+
+    tp = _time(torch, plain, 10, 2)
+    cells = len(batch["blocks"]) * batch["block_cells"]
+    plan.close()
+    return {"workload": "4096 blocks x 512 cells, N_b ~ U{1..16}, D = 3", "n_cells": cells,
+            "batched_ms": tb, "plain_per_n_ms": tp, "batched_over_plain": tb / tp,
+            "batched_cells_per_s": cells / (tb * 1e-3),
+            "lane_max": lane_max, "persistent_mfma_grid": persistent}
+
+
+def extra_measurements(torch, ops, workloads, dev):
     ex = {}
     for name in ("n4_3d", "n8_adjoint_3d", "n1_closed_form"):
         dd = workloads.make(name)

@@ -181,6 +181,11 @@ int drag_expm_apply_batched(drag_plan *plan, const double *fields,
 int drag_plan_autotune(drag_plan *plan, const double *fields,
                        const double *v_in, double *v_out,
                        drag_stream_t stream, int32_t *lane_max_out);
+/* The plan's current launch configuration: the lane-mapping bound and
+ * whether the MFMA branch runs as a persistent grid over the item queue (1)
+ * or as a plain grid over its blocks (0). */
+int drag_plan_config(const drag_plan *plan, int32_t *lane_max,
+                     int32_t *persistent);
 int drag_plan_destroy(drag_plan *plan);
 
 /* ---- status and introspection -------------------------------------------- */

@@ -75,8 +75,9 @@ __global__ void __launch_bounds__(256) k_batched_wave(BatchArgs B) {
   for (;;) {
     int idx = 0;
     if (lane == 0) idx = (int)atomicAdd(B.counter, 1u);
-    idx = __shfl(idx, 0, 64);
-    if (idx >= B.n_items) break;  // uniform: every wavefront leaves once the queue is empty
+    // wave-uniform from here on: the item and its pointers live in SGPRs
+    idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
+    if (idx >= B.n_items) break;  // every wavefront leaves once the queue is empty
     const BatchItem it = B.items[idx];
     const CellArgs A = block_args(B, it);
     for (int k = 0; k < it.count; ++k)
@@ -84,11 +85,32 @@ __global__ void __launch_bounds__(256) k_batched_wave(BatchArgs B) {
   }
 }
 
+// The same MFMA work as a plain grid: workgroup w takes 4 consecutive cells
+// of one wave-mapped block (one per wavefront).  No loop, so none of the
+// loop-invariant state the persistent grid keeps live across items; the
+// hardware dispatcher balances the workgroups.  The autotuner picks between
+// the two.
+__global__ void __launch_bounds__(256) k_batched_wave_grid(BatchArgs B, int groups_per_block,
+                                                           int xcd_blocks) {
+  __shared__ double lds[4 * 2 * kStageDoubles];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // XCD-aware order (the grid is a multiple of 8): each XCD gets a
+  // contiguous run of workgroups, hence whole blocks
+  const int wg = (blockIdx.x & 7) * xcd_blocks + (blockIdx.x >> 3);
+  const int item = __builtin_amdgcn_readfirstlane(wg / groups_per_block);
+  const int cell = __builtin_amdgcn_readfirstlane((wg % groups_per_block) * 4 + w);
+  if (item >= B.n_items || cell >= B.block_cells) return;  // uniform over the wavefront
+  const BatchItem it = B.items[item];  // one whole block
+  double* bufX = lds + (2 * w) * kStageDoubles;
+  const CellArgs A = block_args(B, it);
+  wave_forward_cell(A, it.n, cell, lane, bufX, bufX + kStageDoubles);
+}
+
 // One 64-cell lane item per wavefront, all items of one species count N.
 template <int N>
 __global__ void __launch_bounds__(256) k_batched_lane(BatchArgs B) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int idx = blockIdx.x * 4 + w;
+  const int idx = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
   if (idx >= B.n_items) return;  // uniform over the wavefront
   const BatchItem it = B.items[idx];
   const CellArgs A = block_args(B, it);

@@ -235,11 +235,17 @@ static bool overlap(Range a, Range b) {
 constexpr int kBatchVariants = 5;
 constexpr int kBatchLmax[kBatchVariants] = {4, 5, 6, 7, 8};
 constexpr int kWaveItemCells = 8;
+// how the MFMA branch runs: a persistent grid over the item queue, or a
+// plain grid over the blocks
+constexpr int kWavePersistent = 0;
+constexpr int kWaveGrid = 1;
 
 struct BatchVariant {
   int lmax = 6;
   BatchItem* d_wave = nullptr;  // MFMA queue (blocks with N > lmax)
   int n_wave = 0;
+  BatchItem* d_wave_blocks = nullptr;  // the same blocks whole, for the plain grid
+  int n_wave_blocks = 0;
   BatchItem* d_lane[kLaneMaxN + 1] = {};  // 64-cell lane items per N <= lmax
   int n_lane[kLaneMaxN + 1] = {};
 };
@@ -272,6 +278,7 @@ struct drag_plan {
   std::vector<int64_t> field_off, v_off;
   int64_t fields_total = 0, v_total = 0;
   int lmax = 6;
+  int wave_mode = dragexp::kWaveGrid;
   dragexp::BatchVariant var[dragexp::kBatchVariants];
   int wave_grid = 0;
   int64_t* d_field_off = nullptr;
@@ -285,6 +292,7 @@ struct drag_plan {
   const double* g_vin = nullptr;
   double* g_vout = nullptr;
   int g_lmax = 0;
+  int g_mode = -1;
 };
 
 namespace dragexp {
@@ -297,6 +305,7 @@ static void plan_drop_graph(drag_plan* P) {
   P->g_fields = P->g_vin = nullptr;
   P->g_vout = nullptr;
   P->g_lmax = 0;
+  P->g_mode = -1;
 }
 
 static void plan_free(drag_plan* P) {
@@ -307,6 +316,7 @@ static void plan_free(drag_plan* P) {
   if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
   for (BatchVariant& V : P->var) {
     if (V.d_wave) (void)hipFree(V.d_wave);
+    if (V.d_wave_blocks) (void)hipFree(V.d_wave_blocks);
     for (BatchItem* p : V.d_lane)
       if (p) (void)hipFree(p);
   }
@@ -350,11 +360,12 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
   for (int v = 0; v < kBatchVariants; ++v) {
     BatchVariant& V = P->var[v];
     V.lmax = kBatchLmax[v];
-    std::vector<BatchItem> wave;
+    std::vector<BatchItem> wave, wave_blocks;
     std::vector<BatchItem> lane[kLaneMaxN + 1];
     for (int b = 0; b < P->n_blocks; ++b) {
       const int n = P->n_species[b];
       const bool is_lane = n <= V.lmax;
+      if (!is_lane) wave_blocks.push_back(BatchItem{b, n, 0, P->block_cells});
       const int step = is_lane ? 64 : kWaveItemCells;
       for (int first = 0; first < P->block_cells; first += step) {
         const BatchItem it{b, n, first, std::min(step, P->block_cells - first)};
@@ -363,7 +374,9 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
       }
     }
     V.n_wave = (int)wave.size();
+    V.n_wave_blocks = (int)wave_blocks.size();
     int rc = upload(&V.d_wave, wave);
+    if (!rc) rc = upload(&V.d_wave_blocks, wave_blocks);
     for (int n = 1; n <= kLaneMaxN && !rc; ++n) {
       V.n_lane[n] = (int)lane[n].size();
       rc = upload(&V.d_lane[n], lane[n]);
@@ -398,8 +411,8 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
 
 // Enqueue one batched update (variant lmax) on `main`, the lane grids on
 // `side` between a fork and a join: captured, this is the plan's graph.
-static int plan_enqueue(drag_plan* P, int lmax, const double* fields, const double* v_in,
-                        double* v_out, hipStream_t main, hipStream_t side) {
+static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
+                        const double* v_in, double* v_out, hipStream_t main, hipStream_t side) {
   int v = 0;
   while (v + 1 < kBatchVariants && kBatchLmax[v] != lmax) ++v;
   const BatchVariant& V = P->var[v];
@@ -415,24 +428,33 @@ static int plan_enqueue(drag_plan* P, int lmax, const double* fields, const doub
     batched_lane(n, L, side);
   }
   if (hipEventRecord(P->ev_join, side) != hipSuccess) return DRAG_ERR_HIP;
-  if (V.n_wave > 0) {
+  if (V.n_wave > 0 && mode == kWavePersistent) {
     BatchArgs W = B;
     W.items = V.d_wave;
     W.n_items = V.n_wave;
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, main, P->d_counter);
     hipLaunchKernelGGL(k_batched_wave, dim3(P->wave_grid), dim3(256), 0, main, W);
+  } else if (V.n_wave > 0) {
+    BatchArgs W = B;
+    W.items = V.d_wave_blocks;
+    W.n_items = V.n_wave_blocks;
+    const int gpb = (P->block_cells + 3) / 4;
+    const Grid gr = grid_for((int64_t)V.n_wave_blocks * gpb);
+    hipLaunchKernelGGL(k_batched_wave_grid, dim3(gr.blocks), dim3(256), 0, main, W, gpb,
+                       gr.xcd_blocks);
   }
   if (hipStreamWaitEvent(main, P->ev_join, 0) != hipSuccess) return DRAG_ERR_HIP;
   return hip_status(hipGetLastError());
 }
 
 // Capture the update for these pointers and this lmax into the plan's graph.
-static int plan_capture(drag_plan* P, int lmax, const double* fields, const double* v_in,
-                        double* v_out) {
+static int plan_capture(drag_plan* P, int lmax, int mode, const double* fields,
+                        const double* v_in, double* v_out) {
   plan_drop_graph(P);
   if (hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return DRAG_ERR_HIP;
-  const int rc = plan_enqueue(P, lmax, fields, v_in, v_out, P->cap_stream, P->side_stream);
+  const int rc =
+      plan_enqueue(P, lmax, mode, fields, v_in, v_out, P->cap_stream, P->side_stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
   if (rc || e != hipSuccess) {
@@ -448,6 +470,7 @@ static int plan_capture(drag_plan* P, int lmax, const double* fields, const doub
   P->g_vin = v_in;
   P->g_vout = v_out;
   P->g_lmax = lmax;
+  P->g_mode = mode;
   return DRAG_OK;
 }
 
@@ -588,8 +611,8 @@ int drag_expm_apply_batched(drag_plan* P, const double* fields, const double* v_
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != P->device) return DRAG_ERR_PLAN;
   if (!P->exec || P->g_fields != fields || P->g_vin != v_in || P->g_vout != v_out ||
-      P->g_lmax != P->lmax) {
-    const int rc = plan_capture(P, P->lmax, fields, v_in, v_out);
+      P->g_lmax != P->lmax || P->g_mode != P->wave_mode) {
+    const int rc = plan_capture(P, P->lmax, P->wave_mode, fields, v_in, v_out);
     if (rc) return rc;
   }
   return hip_status(hipGraphLaunch(P->exec, (hipStream_t)stream));
@@ -611,22 +634,27 @@ int drag_plan_autotune(drag_plan* P, const double* fields, const double* v_in, d
     return DRAG_ERR_HIP;
   }
   float best_ms = 0.0f;
-  int best = P->lmax, rc = DRAG_OK;
-  for (int v = 0; v < kBatchVariants && rc == DRAG_OK; ++v) {
-    rc = plan_capture(P, kBatchLmax[v], fields, v_in, v_out);
-    float ms = 0.0f;
-    for (int rep = 0; rep < 3 && rc == DRAG_OK; ++rep) {  // rep 0 warms up
-      rc = hip_status(hipEventRecord(e0, st));
-      if (!rc) rc = hip_status(hipGraphLaunch(P->exec, st));
-      if (!rc) rc = hip_status(hipEventRecord(e1, st));
-      if (!rc) rc = hip_status(hipEventSynchronize(e1));
-      float t = 0.0f;
-      if (!rc) rc = hip_status(hipEventElapsedTime(&t, e0, e1));
-      if (rep == 1 || (rep > 1 && t < ms)) ms = t;
-    }
-    if (!rc && (v == 0 || ms < best_ms)) {
-      best_ms = ms;
-      best = kBatchLmax[v];
+  int best = P->lmax, best_mode = P->wave_mode, rc = DRAG_OK;
+  bool have = false;
+  for (int mode = 0; mode < 2 && rc == DRAG_OK; ++mode) {
+    for (int v = 0; v < kBatchVariants && rc == DRAG_OK; ++v) {
+      rc = plan_capture(P, kBatchLmax[v], mode, fields, v_in, v_out);
+      float ms = 0.0f;
+      for (int rep = 0; rep < 3 && rc == DRAG_OK; ++rep) {  // rep 0 warms up
+        rc = hip_status(hipEventRecord(e0, st));
+        if (!rc) rc = hip_status(hipGraphLaunch(P->exec, st));
+        if (!rc) rc = hip_status(hipEventRecord(e1, st));
+        if (!rc) rc = hip_status(hipEventSynchronize(e1));
+        float t = 0.0f;
+        if (!rc) rc = hip_status(hipEventElapsedTime(&t, e0, e1));
+        if (rep == 1 || (rep > 1 && t < ms)) ms = t;
+      }
+      if (!rc && (!have || ms < best_ms)) {
+        have = true;
+        best_ms = ms;
+        best = kBatchLmax[v];
+        best_mode = mode;
+      }
     }
   }
   (void)hipEventDestroy(e0);
@@ -634,7 +662,15 @@ int drag_plan_autotune(drag_plan* P, const double* fields, const double* v_in, d
   plan_drop_graph(P);
   if (rc) return rc;
   P->lmax = best;
+  P->wave_mode = best_mode;
   if (lane_max_out) *lane_max_out = best;
+  return DRAG_OK;
+}
+
+int drag_plan_config(const drag_plan* P, int32_t* lane_max, int32_t* persistent) {
+  if (!P) return DRAG_ERR_PLAN;
+  if (lane_max) *lane_max = P->lmax;
+  if (persistent) *persistent = P->wave_mode == kWavePersistent ? 1 : 0;
   return DRAG_OK;
 }
 

@@ -263,6 +263,13 @@ class BatchPlan:
                                                  ctypes.byref(lm)), "drag_plan_autotune")
         return lm.value
 
+    def config(self):
+        """(lane_max, persistent) of the current launch configuration."""
+        lm, pe = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.lib().drag_plan_config(self._plan, ctypes.byref(lm), ctypes.byref(pe)),
+                   "drag_plan_config")
+        return lm.value, bool(pe.value)
+
     def close(self):
         if getattr(self, "_plan", None) is not None and self._plan.value:
             _lib.lib().drag_plan_destroy(self._plan)

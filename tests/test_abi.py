@@ -131,6 +131,7 @@ def test_batched_plan_argument_errors(L):
     assert L.drag_plan_batched(ctypes.byref(dd), ctypes.byref(plan)) == _lib.ERR_N_SPECIES
     assert L.drag_expm_apply_batched(None, None, None, None, None) == _lib.ERR_PLAN
     assert L.drag_plan_offsets(None, None, None, None, None) == _lib.ERR_PLAN
+    assert L.drag_plan_config(None, None, None) == _lib.ERR_PLAN
     assert L.drag_plan_destroy(None) == _lib.OK
 
 
