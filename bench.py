@@ -63,6 +63,38 @@ def algorithmic_bytes(C, N, D):
     return 8.0 * C * (1 + 2 * N + 2 * D * (N + 1))
 
 
+def source_hash():
+    """Short SHA-256 over the HIP sources; a profile summary records the hash
+    of the sources its counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2509_25347_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 summary of this kernel
+    and workload (FETCH_SIZE + WRITE_SIZE scaled by the copy calibration), or
+    None when there is none or the sources have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("hbm_bytes_per_launch", "source_sha256"):
+                k, v = line.split(":", 1)
+                fields[k] = v.strip()
+    if fields.get("source_sha256") != source_hash() or "hbm_bytes_per_launch" not in fields:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(d, budget_s=12.0, chunk=4096):
     """The oracle (single thread) on a bounded prefix of the same workload."""
     import oracle
@@ -158,7 +190,7 @@ def main():
         "peak": FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved_tflops / FP64_PEAK_TFLOPS, 4),
-        "traffic": None,
+        "traffic": profiled_traffic(f"k_forward_{mapping}", name),
         "kernel": f"k_forward_{mapping}<{N}>",
         "flops_per_launch": f_alg,
         "executed_flops_per_launch": f_exe,
