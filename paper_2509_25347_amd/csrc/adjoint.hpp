@@ -484,4 +484,244 @@ __global__ void __launch_bounds__(256) k_backward_wave(BackArgs A, int xcd_block
   }
 }
 
+// ---- N <= 8: the block form on one 16 x 16 tile -------------------------------
+//
+// For a polynomial f, f([[X, E], [0, X]]) = [[f(X), L_f(X, E)], [0, f(X)]],
+// and the approximant R is a polynomial stage followed by squarings, so one
+// evaluation of R on the 2N x 2N block matrix
+//     Xh = [[B, dB], [0, B]],  B = 2^-s At^T,  dB = 2^-s G
+// with the same (k*, m*, s*) yields Y = R(At^T) - I and dY = L_R(At^T, G)
+// together: each squaring Yh <- 2 Yh + Yh Yh is one 16 x 16 product instead
+// of the three of the separate recurrences.  The blocks sit at offsets 0 and
+// 8 of the tile (species i of the first block is row / column i, of the
+// second 8 + i); rows and columns of species >= N are zero.  A wavefront
+// takes a quad of cells, set up once as in the forward kernel.
+
+__device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, const int N,
+                                                         int64_t c0, int lane, double* lds) {
+  const int g = lane >> 4, j = lane & 15;
+  const int jj = j & 7;  // species of this lane's column in either block
+  const int64_t ld = A.ld;
+  const int n1 = N + 1;
+  const int D = A.n_dim;
+  const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
+  double* stage = lds;
+  double* qa = lds + kStageDoubles;
+  double* qe = qa + 64;
+  double* qp = qe + 64;
+
+  const QuadCell Q = quad_setup(A.rho_g, A.rho_d, A.t_stop, A.n_cells, ld, A.dt, A.k_max,
+                                A.option, N, c0, g, j, qa, qe, qp);
+  const int diag_slot = j * kLdsStride + j;
+
+  // velocity and weight data, lane (g = component, j): species jj
+  const bool comp = g < D;
+  const bool cj = comp && jj < N;
+  auto load_vw = [&](int64_t cell, double& v0, double& vj, double& w0, double& wj) {
+    v0 = vj = w0 = wj = 0.0;
+    if (comp && cell < A.n_cells) {
+      const int64_t base = (int64_t)(g * n1) * ld + cell;
+      v0 = A.v_in[base];
+      w0 = A.w[base];
+      if (jj < N) {
+        vj = A.v_in[base + (int64_t)(1 + jj) * ld];
+        wj = A.w[base + (int64_t)(1 + jj) * ld];
+      }
+    }
+  };
+  double v0n, vjn, w0n, wjn;
+  load_vw(c0, v0n, vjn, w0n, wjn);
+
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int64_t cell = c0 + c;
+    if (cell >= A.n_cells) break;  // uniform
+    const double v0 = v0n, vj = vjn, w0 = w0n, wj = wjn;
+    if (c < 3) load_vw(cell + 1, v0n, vjn, w0n, wjn);  // prefetch the next cell
+
+    unsigned bad = (unsigned)__builtin_amdgcn_readlane((int)Q.bad, 16 * c);
+    const bool fin = isfinite(v0) && isfinite(vj) && isfinite(w0) && isfinite(wj);
+    if (!__all(fin) && !bad) bad = kBadVelocity;
+    if (bad) {
+      const double qnan = __builtin_nan("");
+      if (lane < D * n1) {
+        if (A.v_out) A.v_out[(int64_t)lane * ld + cell] = qnan;
+        if (A.g_v) A.g_v[(int64_t)lane * ld + cell] = qnan;
+      }
+      if (lane < N) {
+        if (A.g_logt) A.g_logt[lane * ld + cell] = qnan;
+        if (A.g_t) A.g_t[lane * ld + cell] = qnan;
+        if (A.g_rho_d) A.g_rho_d[lane * ld + cell] = qnan;
+      }
+      if (lane == 0) {
+        if (A.g_rho_g) A.g_rho_g[cell] = qnan;
+        atomicOr(&g_status_word, bad);
+      }
+      continue;
+    }
+    const int kp = __builtin_amdgcn_readlane(Q.kpack, 16 * c);
+    const int kk = kp & 15, s = kp >> 4;
+    const int q = kTabQ[kk], r = kTabR[kk];
+    const double sigma = readlane_f64(Q.sig, 16 * c);
+
+    const int sj = 16 * c + quad_slot(jj);
+    const double ej = qe[sj], aj = qa[sj];
+    double nb[2], npb[2];  // -b, -pb of species 4 v + g, v = 0, 1
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int sr = 16 * c + quad_slot(4 * v + g);
+      nb[v] = -ldexp(qa[sr], -s);
+      npb[v] = -ldexp(qp[sr], -s);
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // W_c (lane row g = component c), ubar, dv
+    const double Wsum = row_chain(w0, cj && j < 8 ? wj : 0.0, 8);
+    const double dv = cj ? vj - v0 : 0.0;
+    const double ub = cj ? wj - Wsum * ej / sigma : 0.0;
+
+    // dB = 2^-s G at rows 0..7, columns 8..15: one MFMA over the components
+    // (A[i][c] = ubar_c[i] from lanes j < 8, B[c][8 + k] = dv_c[k] from lanes
+    // j >= 8)
+    v4d Xh = __builtin_amdgcn_mfma_f64_16x16x4f64(j < 8 ? ub : 0.0, j < 8 ? 0.0 : dv, zero4, 0,
+                                                  0, 0);
+    // B = M^T on the diagonal blocks: B[i][k] = -b_i [i == k] - pb_i
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + g;
+      const bool diag_block = (row < 8) == (j < 8);
+      const double bdiag = ((row & 7) == jj) ? nb[v & 1] : 0.0;
+      const double val = (jj < N && (row & 7) < N) ? bdiag + npb[v & 1] : 0.0;
+      Xh[v] = diag_block ? val : ldexp(Xh[v], -s);
+    }
+
+    // powers P_jj = Xh^jj on the matrix cores: Xh is the A operand for all
+    // of them (one LDS transposition), each power the B operand of the next
+    double XA[4];
+    stage_tile(stage, g, j, Xh);
+    load_a_ops(stage, g, j, XA);
+    v4d P[6];
+    P[1] = Xh;
+#pragma unroll
+    for (int p = 2; p <= 5; ++p) {
+      if (p <= q) {
+        double Bp[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Bp[t] = P[p - 1][t];
+        P[p] = mma16(XA, Bp, zero4);
+      } else {
+        P[p] = zero4;
+      }
+    }
+    double Bq[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Bq[t] = P[1][t];
+#pragma unroll
+    for (int p = 2; p <= 5; ++p)
+      if (p == q) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Bq[t] = P[p][t];
+      }
+    auto bbar = [&](int k) {
+      v4d acc = zero4;
+#pragma unroll
+      for (int p = 1; p <= 5; ++p) {
+        if (p <= q) {
+          const double cf = kInvFact[q * k + p];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[v] = fma(cf, P[p][v], acc[v]);
+        }
+      }
+      return acc;
+    };
+    v4d F = bbar(r - 1);
+    for (int k = r - 2; k >= 0; --k) {
+      double Af[4];
+      stage_tile(stage, g, j, F);
+      load_a_ops(stage, g, j, Af);
+      F = mma16(Af, Bq, bbar(k));
+    }
+    // squarings of the block matrix, (Yh + 2 I) Yh
+    v4d Y = F;
+    int it = 0;
+    for (; it + 2 <= s; it += 2) {
+      const v4d Y1 = square_step(Y, stage, g, j, diag_slot);
+      Y = square_step(Y1, stage, g, j, diag_slot);
+    }
+    if (it < s) Y = square_step(Y, stage, g, j, diag_slot);
+
+    // Y = Z^T in the upper-left block, dY = dL/dAt in the upper-right.
+    // u_c = Z dv_c = (dV^T Y)[c] and Z^T ubar_c = (Ubar^T Y^T)[c]: A operands
+    // rows = components (lane (g, i) takes component i, species 4t+g).
+    double YB[4], ZB[4], DvA[4], UbA[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) YB[t] = Y[t];
+    stage_tile(stage, g, j, Y);
+    load_a_ops(stage, g, j, ZB);  // Yh^T as the B operand
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int src = (j < D && t < 2) ? 16 * j + 4 * t + g : 0;
+      const double a1 = __shfl(dv, src, 64), a2 = __shfl(ub, src, 64);
+      DvA[t] = (j < D && t < 2) ? a1 : 0.0;
+      UbA[t] = (j < D && t < 2) ? a2 : 0.0;
+    }
+    const v4d Um = mma16(DvA, YB, zero4);  // lane (g, j) [0]: u_g[j]
+    const v4d Vm = mma16(UbA, ZB, zero4);  // lane (g, j) [0]: (Z^T ubar_g)_j
+    const double u = (cj && j < 8) ? Um[0] : 0.0;
+    const double zt = (cj && j < 8) ? Vm[0] : 0.0;
+    const double eu = row_chain(0.0, ej * u, 8);
+    const double d0 = -eu / sigma;
+    const double zt_sum = row_chain(0.0, zt, 8);
+    if (comp && j < 8) {
+      const int64_t base = (int64_t)(g * n1) * ld + cell;
+      if (A.v_out) {
+        if (jj < N) A.v_out[base + (int64_t)(1 + jj) * ld] = vj + (d0 + u);
+        if (j == 0) A.v_out[base] = v0 + d0;
+      }
+      if (A.g_v) {
+        if (jj < N) A.g_v[base + (int64_t)(1 + jj) * ld] = wj + zt;
+        if (j == 0) A.g_v[base] = w0 - zt_sum;
+      }
+    }
+    // direct dependence of the gas update on e, summed over components
+    const double ge_dir = groups_sum(cj ? (-d0 - u) * (Wsum / sigma) : 0.0);
+    // column sums and diagonal of dY (upper-right block, rows 4v+g, v < 2,
+    // column 8 + k), moved to lane k of each row
+    double col = (j < 8) ? 0.0 : Y[0] + Y[1];
+    double dg = 0.0;
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+      if (j >= 8 && 4 * v + g == jj) dg = Y[v];
+    col = row_ror64<8>(groups_sum(col));
+    dg = row_ror64<8>(groups_sum(dg));
+    if (g == 0) {
+      const double rg = A.rho_g[cell];
+      double ge = 0.0;
+      if (j < N) {
+        const double ga = -dg - ej * col;
+        ge = -aj * col + ge_dir;
+        const double glt = -aj * ga;
+        if (A.g_logt) A.g_logt[j * ld + cell] = glt;
+        if (A.g_t) A.g_t[j * ld + cell] = glt / A.t_stop[j * ld + cell];
+        if (A.g_rho_d) A.g_rho_d[j * ld + cell] = ge / rg;
+      }
+      const double sum_ege = row_chain(0.0, ej * ge, N);
+      if (j == 0 && A.g_rho_g) A.g_rho_g[cell] = -sum_ege / rg;
+    }
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_backward_block(BackArgs A, int xcd_blocks) {
+  static_assert(N <= 8, "the block form needs 2N <= 16");
+  __shared__ double lds[4 * kQuadDoubles];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int64_t c0 = (logical * 4 + w) * 4;
+  if (c0 >= A.n_cells) return;  // uniform over the wavefront
+  wave_backward_block_quad(A, N, c0, lane, lds + w * kQuadDoubles);
+}
+
 }  // namespace dragexp

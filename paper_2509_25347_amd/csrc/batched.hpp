@@ -68,10 +68,9 @@ __device__ __forceinline__ CellArgs block_args(const BatchArgs& B, const BatchIt
 
 // Persistent MFMA grid over the queue of wave items.
 __global__ void __launch_bounds__(256) k_batched_wave(BatchArgs B) {
-  __shared__ double lds[4 * 2 * kStageDoubles];
+  __shared__ double lds[4 * kQuadDoubles];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* bufX = lds + (2 * w) * kStageDoubles;
-  double* bufY = bufX + kStageDoubles;
+  double* mine = lds + w * kQuadDoubles;
   for (;;) {
     int idx = 0;
     if (lane == 0) idx = (int)atomicAdd(B.counter, 1u);
@@ -79,31 +78,32 @@ __global__ void __launch_bounds__(256) k_batched_wave(BatchArgs B) {
     idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
     if (idx >= B.n_items) break;  // every wavefront leaves once the queue is empty
     const BatchItem it = B.items[idx];
-    const CellArgs A = block_args(B, it);
-    for (int k = 0; k < it.count; ++k)
-      wave_forward_cell(A, it.n, (int64_t)it.first + k, lane, bufX, bufY);
+    CellArgs A = block_args(B, it);
+    A.n_cells = (int64_t)it.first + it.count;  // quads stay inside the item
+    for (int k = 0; k < it.count; k += 4)
+      wave_forward_quad(A, it.n, (int64_t)it.first + k, lane, mine);
   }
 }
 
-// The same MFMA work as a plain grid: workgroup w takes 4 consecutive cells
-// of one wave-mapped block (one per wavefront).  No loop, so none of the
+// The same MFMA work as a plain grid: workgroup w takes 16 consecutive cells
+// of one wave-mapped block (a quad per wavefront).  No loop, so none of the
 // loop-invariant state the persistent grid keeps live across items; the
 // hardware dispatcher balances the workgroups.  The autotuner picks between
 // the two.
 __global__ void __launch_bounds__(256) k_batched_wave_grid(BatchArgs B, int groups_per_block,
                                                            int xcd_blocks) {
-  __shared__ double lds[4 * 2 * kStageDoubles];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ double lds[4 * kQuadDoubles];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   // XCD-aware order (the grid is a multiple of 8): each XCD gets a
   // contiguous run of workgroups, hence whole blocks
   const int wg = (blockIdx.x & 7) * xcd_blocks + (blockIdx.x >> 3);
   const int item = __builtin_amdgcn_readfirstlane(wg / groups_per_block);
-  const int cell = __builtin_amdgcn_readfirstlane((wg % groups_per_block) * 4 + w);
-  if (item >= B.n_items || cell >= B.block_cells) return;  // uniform over the wavefront
+  const int c0 = __builtin_amdgcn_readfirstlane((wg % groups_per_block) * 16 + 4 * w);
+  if (item >= B.n_items || c0 >= B.block_cells) return;  // uniform over the wavefront
   const BatchItem it = B.items[item];  // one whole block
-  double* bufX = lds + (2 * w) * kStageDoubles;
   const CellArgs A = block_args(B, it);
-  wave_forward_cell(A, it.n, cell, lane, bufX, bufX + kStageDoubles);
+  wave_forward_quad(A, it.n, c0, lane, lds + w * kQuadDoubles);
 }
 
 // One 64-cell lane item per wavefront, all items of one species count N.

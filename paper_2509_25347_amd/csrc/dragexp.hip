@@ -106,7 +106,7 @@ static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
 
 template <int N>
 static int launch_forward_wave(const CellArgs& A, hipStream_t st) {
-  const Grid gr = grid_for((A.n_cells + 3) / 4);
+  const Grid gr = grid_for((A.n_cells + 15) / 16);  // a quad of cells per wavefront
   hipLaunchKernelGGL(k_forward_wave<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
   return hip_status(hipGetLastError());
 }
@@ -128,11 +128,19 @@ static int launch_backward_wave(const BackArgs& A, hipStream_t st) {
   return hip_status(hipGetLastError());
 }
 
+// N <= 8: the block form (both blocks of [[B, dB], [0, B]] on one tile).
+template <int N>
+static int launch_backward_block(const BackArgs& A, hipStream_t st) {
+  const Grid gr = grid_for((A.n_cells + 15) / 16);  // a quad of cells per wavefront
+  hipLaunchKernelGGL(k_backward_block<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
 static BwdFn wave_bwd(int N) {
   static const BwdFn tab[16] = {
-      launch_backward_wave<1>,  launch_backward_wave<2>,  launch_backward_wave<3>,
-      launch_backward_wave<4>,  launch_backward_wave<5>,  launch_backward_wave<6>,
-      launch_backward_wave<7>,  launch_backward_wave<8>,  launch_backward_wave<9>,
+      launch_backward_block<1>, launch_backward_block<2>, launch_backward_block<3>,
+      launch_backward_block<4>, launch_backward_block<5>, launch_backward_block<6>,
+      launch_backward_block<7>, launch_backward_block<8>, launch_backward_wave<9>,
       launch_backward_wave<10>, launch_backward_wave<11>, launch_backward_wave<12>,
       launch_backward_wave<13>, launch_backward_wave<14>, launch_backward_wave<15>,
       launch_backward_wave<16>};
@@ -438,7 +446,7 @@ static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
     BatchArgs W = B;
     W.items = V.d_wave_blocks;
     W.n_items = V.n_wave_blocks;
-    const int gpb = (P->block_cells + 3) / 4;
+    const int gpb = (P->block_cells + 15) / 16;
     const Grid gr = grid_for((int64_t)V.n_wave_blocks * gpb);
     hipLaunchKernelGGL(k_batched_wave_grid, dim3(gr.blocks), dim3(256), 0, main, W, gpb,
                        gr.xcd_blocks);

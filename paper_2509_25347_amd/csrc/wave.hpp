@@ -1,11 +1,12 @@
-// wave.hpp -- one cell per 64-lane wavefront, FP64 MFMA (v_mfma_f64_16x16x4).
+// wave.hpp -- the MFMA mapping: a cell's exponential on a whole 64-lane
+// wavefront, FP64 MFMA (v_mfma_f64_16x16x4).
 //
 // The cell's relative-velocity matrix (the N x N reduced form described in
 // lane.hpp) is held as one 16 x 16 tile, zero-padded when N < 16: the
 // species block of the drag problem is exactly the MFMA tile for N = 16.
-// Every dense product of the method -- the powers of the scaled matrix, the
-// Horner steps of the Paterson-Stockmeyer evaluation and the s squarings --
-// is a chain of four 16x16x4 FP64 MFMAs (k = 16).
+// Dense products of the method (Horner steps of the Paterson-Stockmeyer
+// evaluation, the s squarings, the apply) are chains of four 16x16x4 FP64
+// MFMAs (k = 16).
 //
 // Register layouts of v_mfma_f64_16x16x4 (lane l = 16 g + j, g = l / 16):
 //   A operand (16 x 4, step t):  A[i = j][4t + g]
@@ -64,7 +65,7 @@ __device__ __forceinline__ v4d mma16(const double (&A)[4], const double (&B)[4],
   return acc;
 }
 
-// Per-cell set-up of the wave kernel: the lane with j = lane % 16 < N owns
+// Per-cell set-up of the MFMA adjoint: the lane with j = lane % 16 < N owns
 // species j.  Every lane computes the norm's sums in ascending species
 // order from broadcast values, so ||A||_1 is the same bits as the
 // definition.  Returns the bad-input bits (uniform over the wavefront).
@@ -115,166 +116,366 @@ __device__ __forceinline__ void wave_setup(WaveCell& W, const int N, const doubl
   W.kms = bad ? Kms{1, 2, 0} : select_kms(nrm, K, option);
 }
 
-// Z = T_m(2^-s At)^(2^s) - I in the D layout (rows 4v+g, column j).
-__device__ __forceinline__ v4d wave_expm(const WaveCell& W, const int N, int g, int j,
-                                         double* bufX, double* bufY) {
-  const int s = W.kms.s;
-  const int q = kTabQ[W.kms.k], r = kTabR[W.kms.k];
-  const double bj = ldexp(W.aj, -s);
-  const double pbj = ldexp(W.pj, -s);
+// ---- the forward update: four cells per wavefront ---------------------------
+//
+// One wavefront takes a quad of four consecutive cells.  The set-up (loads,
+// coefficients, ||A||_1, Alg. 1) runs once for the quad with lane 16 g + j
+// holding species j of cell g, so every 16-lane row of the wavefront is one
+// cell and the row-wise sums of the norm are DPP broadcasts.  The
+// exponential then runs cell by cell on the whole wavefront:
+//   * products by the scaled matrix M = -diag(b) - 1 pb^T (the powers of the
+//     Paterson-Stockmeyer stage) are its diagonal-plus-rank-one form, on the
+//     vector ALU: a 16-row weighted column sum and one FMA per element;
+//   * the Horner steps and the squarings are dense 16 x 16 products on the
+//     matrix cores.  Their B operand is the D layout itself (lane 16 g + j,
+//     register t holds row 4 t + g, column j), so only the A operand goes
+//     through a 16 x 17 LDS tile;
+//   * each squaring Z <- 2 Z + Z Z is issued as (Z + 2 I) Z: 2 I is added to
+//     the staged copy by one LDS add on the diagonal, so no vector
+//     instruction is spent on 2 Z.
 
-  // M = 2^-s At, D layout: M[row][j] = -b_row [row == j] - pb_j (row, j < N)
-  v4d M;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = 4 * v + g;
-    M[v] = (row < N && j < N) ? ((row == j ? -bj : 0.0) - pbj) : 0.0;
-  }
-  // M as the A operand: M[i = j][col = 4t + g]
-  double Ma[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int col = 4 * t + g;
-    const double pbc = __shfl(pbj, col, 64);
-    Ma[t] = (j < N && col < N) ? ((j == col ? -bj : 0.0) - pbc) : 0.0;
-  }
+// Broadcast lane L of every 16-lane row to the whole row (DPP row_newbcast).
+template <int L>
+__device__ __forceinline__ double row_bcast(double x) {
+  return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + L, 0xf, 0xf, true);
+}
 
-  // powers P_1 = M, P_jj = M P_{jj-1} (Sect. 2.3: the power sequence of
-  // the Paterson-Stockmeyer evaluation, q <= 5)
-  v4d P[6];
+// A 64-bit value rotated by R lanes within each 16-lane row (two 32-bit DPP
+// moves; 64-bit DPP only has the broadcast form).
+template <int R>
+__device__ __forceinline__ double row_ror64(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x120 + R, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x120 + R, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int R>
+__device__ __forceinline__ unsigned row_ror32(unsigned x) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x120 + R, 0xf, 0xf, true);
+}
+
+__device__ __forceinline__ double row_max(double x) {
+  x = fmax(x, row_ror64<8>(x));
+  x = fmax(x, row_ror64<4>(x));
+  x = fmax(x, row_ror64<2>(x));
+  return fmax(x, row_ror64<1>(x));
+}
+
+__device__ __forceinline__ unsigned row_or(unsigned x) {
+  x |= row_ror32<8>(x);
+  x |= row_ror32<4>(x);
+  x |= row_ror32<2>(x);
+  return x | row_ror32<1>(x);
+}
+
+// x(lane 16 g + j) summed over the four rows g, (x0 + x1) + (x2 + x3), the
+// same bits in every row (v_permlane16_swap / v_permlane32_swap exchange
+// rows 0 <-> 1, 2 <-> 3 and 0,1 <-> 2,3).
+__device__ __forceinline__ double swap_sum16(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32),
+                                                   false, false);
+  const double d0 = __builtin_bit_cast(double, ((long long)hi[0] << 32) | lo[0]);
+  const double d1 = __builtin_bit_cast(double, ((long long)hi[1] << 32) | lo[1]);
+  return d0 + d1;
+}
+
+__device__ __forceinline__ double swap_sum32(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32),
+                                                   false, false);
+  const double d0 = __builtin_bit_cast(double, ((long long)hi[0] << 32) | lo[0]);
+  const double d1 = __builtin_bit_cast(double, ((long long)hi[1] << 32) | lo[1]);
+  return d0 + d1;
+}
+
+__device__ __forceinline__ double sum_rows(double x) { return swap_sum32(swap_sum16(x)); }
+
+// Sequential row sum init + x(lane 0) + x(lane 1) + ... + x(lane N-1) of every
+// row: one rounding per addition, ascending species order.
+template <int L = 0>
+__device__ __forceinline__ double row_chain(double acc, double x, const int N) {
+  if constexpr (L < kMaxSpecies) {
+    if (L < N) return row_chain<L + 1>(acc + row_bcast<L>(x), x, N);
+  }
+  return acc;
+}
+
+// Per-wavefront LDS: the A-operand staging tile and the quad's coefficients.
+// Species j of quad cell c sits at 16 c + (4 (j & 3) + (j >> 2)), so the four
+// species 4 v + g (v = 0..3) that lane 16 g + j needs are contiguous.
+constexpr int kQuadDoubles = kStageDoubles + 3 * 64;
+
+__device__ __forceinline__ int quad_slot(int j) { return 4 * (j & 3) + (j >> 2); }
+
+struct QuadRows {
+  double nb[4];  // -b of rows 4 v + g  (b = 2^-s a)
+  double pb[4];  // pb of rows 4 v + g  (pb = 2^-s p)
+  double nbj, npbj;  // -b_j, -pb_j of column j
+};
+
+// X <- M X for M = -diag(b) - 1 pb^T (rows >= N of the result stay zero).
+__device__ __forceinline__ v4d mul_M(const v4d& X, const QuadRows& R, const double (&rm)[4]) {
+  double part = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) part = fma(R.pb[v], X[v], part);
+  const double cs = -sum_rows(part);  // -(pb^T X)_j
+  v4d Y;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Y[v] = fma(R.nb[v], X[v], cs * rm[v]);
+  return Y;
+}
+
+// T_m(M) - I by the Paterson-Stockmeyer scheme with Q powers (Sect. 2.3):
+// P_jj = M^jj in the structured form, Bbar_k = sum_{jj=1}^{Q} b_{Qk+jj} P_jj,
+// then Horner F = Bbar_{r-1}; F = Bbar_k + F P_Q, k = r-2..0 on the matrix
+// cores (P_Q is the B operand straight from registers).
+template <int Q>
+__device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const double (&rm)[4],
+                                         int r, double* stage, int g, int j) {
+  v4d P[Q + 1];
   P[1] = M;
 #pragma unroll
-  for (int jj = 2; jj <= 5; ++jj) {
-    if (jj <= q) {
-      double Bt[4];
-      stage_tile(bufX, g, j, P[jj - 1]);
-      load_b_ops(bufX, g, j, Bt);
-      P[jj] = mma16(Ma, Bt, v4d{0.0, 0.0, 0.0, 0.0});
-    } else {
-      P[jj] = v4d{0.0, 0.0, 0.0, 0.0};
-    }
-  }
-  v4d Pq = P[1];
+  for (int jj = 2; jj <= Q; ++jj) P[jj] = mul_M(P[jj - 1], R, rm);
+  double Bq[4];
 #pragma unroll
-  for (int jj = 2; jj <= 5; ++jj)
-    if (jj == q) Pq = P[jj];
-
-  // Bbar_k = sum_{jj=1}^{q} b_{qk+jj} P_jj
+  for (int t = 0; t < 4; ++t) Bq[t] = P[Q][t];
   auto bbar = [&](int k) {
     v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int jj = 1; jj <= 5; ++jj) {
-      if (jj <= q) {
-        const double c = kInvFact[q * k + jj];
+    for (int jj = 1; jj <= Q; ++jj) {
+      const double cf = kInvFact[Q * k + jj];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = fma(c, P[jj][v], acc[v]);
-      }
+      for (int v = 0; v < 4; ++v) acc[v] = fma(cf, P[jj][v], acc[v]);
     }
     return acc;
   };
-
-  // Horner: F = Bbar_{r-1}; F = Bbar_k + F P_q, k = r-2..0.  F = T_m(M) - I.
-  double Bq[4];
-  stage_tile(bufY, g, j, Pq);
-  load_b_ops(bufY, g, j, Bq);
   v4d F = bbar(r - 1);
   for (int k = r - 2; k >= 0; --k) {
     double Af[4];
-    stage_tile(bufX, g, j, F);
-    load_a_ops(bufX, g, j, Af);
+    stage_tile(stage, g, j, F);
+    load_a_ops(stage, g, j, Af);
     F = mma16(Af, Bq, bbar(k));
   }
-
-  // squarings, Y-form: Z <- 2 Z + Z Z
-  v4d Z = F;
-  for (int it = 0; it < s; ++it) {
-    double Az[4], Bz[4];
-    stage_tile(bufX, g, j, Z);
-    load_a_ops(bufX, g, j, Az);
-    load_b_ops(bufX, g, j, Bz);
-    Z = mma16(Az, Bz, Z + Z);
-  }
-  return Z;
+  return F;
 }
 
-// The forward update of one cell by a whole wavefront (lane = 0..63), with
-// two 16 x 17 LDS tiles private to the wavefront.
-__device__ __forceinline__ void wave_forward_cell(const CellArgs& A, const int N, int64_t cell,
-                                                  int lane, double* bufX, double* bufY) {
+// One squaring of the Y form, Z <- 2 Z + Z Z, issued as (Z + 2 I) Z: Z is
+// staged, lanes 0..15 add 2 to the diagonal of the staged copy, the copy is
+// read back as the A operand, Z itself is the B operand and the accumulator
+// starts at zero.  The extra rounding of the diagonal entries 2 + Z_jj is
+// of the same size as that of the sum 2 Z + Z Z.
+__device__ __forceinline__ v4d square_step(const v4d& Z, double* stage, int g, int j,
+                                           int diag_slot) {
+  double Az[4], Bz[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) Bz[t] = Z[t];
+  stage_tile(stage, g, j, Z);
+  if (g == 0) atomicAdd(stage + diag_slot, 2.0);
+  __builtin_amdgcn_wave_barrier();
+  load_a_ops(stage, g, j, Az);
+  return mma16(Az, Bz, v4d{0.0, 0.0, 0.0, 0.0});
+}
+
+// The forward update of cells c0 .. c0+3 (those below n_cells) by one
+// wavefront (lane = 0..63) with its private LDS block `lds`.
+// Set-up of a quad (cells c0 .. c0+3, row g = cell c0 + g, lane j = species
+// j): loads, coefficients (Eq. 2: a = dt / t, e = rho_i / rho_g, p = e a),
+// ||A||_1 and Alg. 1.  The coefficients go to the quad's LDS tables (q*),
+// species j >= N as zeros; the per-cell values come back row-uniform.
+struct QuadCell {
+  unsigned bad;  // bad-input bits of the row's cell
+  int kpack;     // k* | s* << 4
+  double sig;    // 1 + sum_i e_i
+};
+
+__device__ __forceinline__ QuadCell quad_setup(const double* rho_g, const double* rho_d,
+                                               const double* t_stop, int64_t n_cells, int64_t ld,
+                                               double dt, int K, int option, const int N,
+                                               int64_t c0, int g, int j, double* qa, double* qe,
+                                               double* qp) {
+  const int64_t cg = c0 + g;
+  double aj = 0.0, ej = 0.0, pj = 0.0;
+  unsigned bad = 0;
+  if (cg < n_cells) {
+    const double rg = rho_g[cg];
+    bad = gas_bad(rg);
+    if (j < N) {
+      const double t = t_stop[j * ld + cg];
+      const double r = rho_d[j * ld + cg];
+      bad |= species_bad(t, r);
+      const Species sp = species_coeffs(dt, t, r, rg);
+      aj = sp.a;
+      ej = sp.e;
+      pj = sp.p;
+    }
+  }
+  constexpr unsigned kNonFinite = 0x100u;
+  if (!(isfinite(aj) && isfinite(pj))) bad |= kNonFinite;
+  bad = row_or(bad);
+  // ||A||_1 = max(gas column, species columns): gas column |A00| + a_1 + ..
+  // + a_N with |A00| = p_1 + .. + p_N, both sums in ascending order as in
+  // the definition; species column j is p_j + a_j.
+  const double s_row = row_chain(0.0, pj, N);
+  const double col0 = row_chain(s_row, aj, N);
+  const double nrm = fmax(col0, row_max(pj + aj));
+  QuadCell Q;
+  Q.sig = row_chain(1.0, ej, N);
+  if ((bad & 0xffu) == 0u && ((bad & kNonFinite) || !isfinite(nrm))) bad = kBadNorm;
+  Q.bad = bad & 0xffu;
+  const Kms km = select_kms(Q.bad ? 0.0 : nrm, K, option);
+  Q.kpack = km.k | (km.s << 4);
+  const int slot = 16 * g + quad_slot(j);
+  qa[slot] = aj;
+  qe[slot] = ej;
+  qp[slot] = pj;
+  __builtin_amdgcn_wave_barrier();
+  return Q;
+}
+
+__device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N, int64_t c0,
+                                                  int lane, double* lds) {
   const int g = lane >> 4, j = lane & 15;
   const int64_t ld = A.ld;
   const int n1 = N + 1;
   const int D = A.n_dim;
+  double* stage = lds;
+  double* qa = lds + kStageDoubles;
+  double* qe = qa + 64;
+  double* qp = qe + 64;
 
-  WaveCell W;
-  wave_setup(W, N, A.rho_g, A.rho_d, A.t_stop, ld, cell, A.dt, A.k_max, A.option, j);
+  const QuadCell Q = quad_setup(A.rho_g, A.rho_d, A.t_stop, A.n_cells, ld, A.dt, A.k_max,
+                                A.option, N, c0, g, j, qa, qe, qp);
+  const unsigned bad = Q.bad;
+  const int kpack = Q.kpack;
+  const double rsig = 1.0 / Q.sig;
 
-  // velocities: lane (g, col = j < D) loads the relative velocities of rows
-  // 4t + g as the B operand of the final product
-  double v0 = 0.0;
-  double Bd[4] = {0.0, 0.0, 0.0, 0.0};
-  bool vfin = true;
-  if (j < D) {
-    v0 = A.v_in[(int64_t)(j * n1) * ld + cell];
-    vfin = isfinite(v0);
+  // lane constants of the tile layout
+  double rm[4];  // 1 for rows < N
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int row = 4 * t + g;
-      if (row < N) {
-        const double x = A.v_in[(int64_t)(j * n1 + 1 + row) * ld + cell];
-        vfin = vfin && isfinite(x);
-        Bd[t] = x - v0;
-      }
+  for (int v = 0; v < 4; ++v) rm[v] = (4 * v + g < N) ? 1.0 : 0.0;
+  const int diag_slot = j * kLdsStride + j;
+
+  // velocities of one cell: lane (g, j < D) holds component j of the gas
+  // (v0) and of species rows 4 v + g (x[v])
+  auto load_v = [&](int64_t cell, double& v0, double (&x)[4]) {
+    v0 = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = 0.0;
+    if (j < D && cell < A.n_cells) {
+      v0 = A.v_in[(int64_t)(j * n1) * ld + cell];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (4 * v + g < N) x[v] = A.v_in[(int64_t)(j * n1 + 1 + 4 * v + g) * ld + cell];
     }
-  }
-  unsigned bad = W.bad | (__all(vfin) ? 0u : kBadVelocity);
-  if (bad) {
-    if (lane < D * n1) A.v_out[(int64_t)lane * ld + cell] = __builtin_nan("");
-    if (lane == 0) atomicOr(&g_status_word, bad);
-    return;
-  }
+  };
+  double v0n, xn[4];
+  load_v(c0, v0n, xn);
 
-  const v4d Z = wave_expm(W, N, g, j, bufX, bufY);
-
-  // u = Z dv for every component at once
-  double Az[4];
-  stage_tile(bufX, g, j, Z);
-  load_a_ops(bufX, g, j, Az);
-  const v4d U = mma16(Az, Bd, v4d{0.0, 0.0, 0.0, 0.0});
-  double eu = 0.0;
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int64_t cell = c0 + c;
+    if (cell >= A.n_cells) break;  // uniform
+    const double v0 = v0n;
+    double x[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = 4 * v + g;
-    const double er = __shfl(W.ej, row, 64);
-    if (row < N) eu = fma(er, U[v], eu);
-  }
-  eu += __shfl_xor(eu, 16, 64);
-  eu += __shfl_xor(eu, 32, 64);
-  const double d0 = -eu / W.sigma;
-  if (j < D) {
+    for (int v = 0; v < 4; ++v) x[v] = xn[v];
+    if (c < 3) load_v(cell + 1, v0n, xn);  // prefetch the next cell
+
+    unsigned cbad = (unsigned)__builtin_amdgcn_readlane((int)bad, 16 * c);
+    bool vfin = isfinite(v0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) vfin = vfin && isfinite(x[v]);
+    if (!__all(vfin) && !cbad) cbad = kBadVelocity;
+    if (cbad) {
+      if (lane < D * n1) A.v_out[(int64_t)lane * ld + cell] = __builtin_nan("");
+      if (lane == 0) atomicOr(&g_status_word, cbad);
+      continue;
+    }
+    const int kp = __builtin_amdgcn_readlane(kpack, 16 * c);
+    const int kk = kp & 15, s = kp >> 4;
+    const int q = kTabQ[kk], r = kTabR[kk];
+    const double crsig = readlane_f64(rsig, 16 * c);
+
+    // scaled coefficients of this cell
+    QuadRows R;
+    {
+      const double* ra = qa + 16 * c + 4 * g;
+      const double* rp = qp + 16 * c + 4 * g;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        R.nb[v] = -ldexp(ra[v], -s);
+        R.pb[v] = ldexp(rp[v], -s);
+      }
+      const int sj = 16 * c + quad_slot(j);
+      R.nbj = -ldexp(qa[sj], -s);
+      R.npbj = -ldexp(qp[sj], -s);
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // M = 2^-s At in the D layout: M[row][j] = -b_row [row == j] - pb_j
+    v4d M;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = 4 * v + g;
-      if (row < N) {
-        const int64_t idx = (int64_t)(j * n1 + 1 + row) * ld + cell;
-        const double x = A.v_in[idx];
-        A.v_out[idx] = x + (d0 + U[v]);
-      }
+      const double dg = (4 * v + g == j) ? 1.0 : 0.0;
+      M[v] = fma(dg, R.nbj, R.npbj * rm[v]);
     }
-    if (g == 0) A.v_out[(int64_t)(j * n1) * ld + cell] = v0 + d0;
+    v4d Z;
+    switch (q) {  // uniform; one code path per power count
+      case 1: Z = quad_poly<1>(M, R, rm, r, stage, g, j); break;
+      case 2: Z = quad_poly<2>(M, R, rm, r, stage, g, j); break;
+      case 3: Z = quad_poly<3>(M, R, rm, r, stage, g, j); break;
+      case 4: Z = quad_poly<4>(M, R, rm, r, stage, g, j); break;
+      default: Z = quad_poly<5>(M, R, rm, r, stage, g, j); break;
+    }
+
+    // squarings Z <- (Z + 2 I) Z, two per trip so that the result and
+    // the operand registers alternate
+    int it = 0;
+    for (; it + 2 <= s; it += 2) {
+      const v4d Z1 = square_step(Z, stage, g, j, diag_slot);
+      Z = square_step(Z1, stage, g, j, diag_slot);
+    }
+    if (it < s) Z = square_step(Z, stage, g, j, diag_slot);
+
+    // u = Z dv for every component at once (B operand: lane (g, j < D) holds
+    // the relative velocities of rows 4 t + g, component j)
+    double Bd[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Bd[t] = (j < D && 4 * t + g < N) ? x[t] - v0 : 0.0;
+    double Az[4];
+    stage_tile(stage, g, j, Z);
+    load_a_ops(stage, g, j, Az);
+    const v4d U = mma16(Az, Bd, v4d{0.0, 0.0, 0.0, 0.0});
+    double eu = 0.0;
+    const double* re = qe + 16 * c + 4 * g;  // e of rows 4 v + g
+#pragma unroll
+    for (int v = 0; v < 4; ++v) eu = fma(re[v], U[v], eu);
+    eu = sum_rows(eu);
+    const double d0 = -eu * crsig;
+    if (j < D) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (4 * v + g < N) A.v_out[(int64_t)(j * n1 + 1 + 4 * v + g) * ld + cell] = x[v] + (d0 + U[v]);
+      }
+      if (g == 0) A.v_out[(int64_t)(j * n1) * ld + cell] = v0 + d0;
+    }
   }
 }
 
 template <int N>
 __global__ void __launch_bounds__(256) k_forward_wave(CellArgs A, int xcd_blocks) {
-  __shared__ double lds[4 * 2 * kStageDoubles];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ double lds[4 * kQuadDoubles];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int bid = blockIdx.x;
   const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
-  const int64_t cell = logical * 4 + w;
-  if (cell >= A.n_cells) return;  // uniform over the wavefront
-  double* bufX = lds + (2 * w) * kStageDoubles;
-  wave_forward_cell(A, N, cell, lane, bufX, bufX + kStageDoubles);
+  const int64_t c0 = (logical * 4 + w) * 4;
+  if (c0 >= A.n_cells) return;  // uniform over the wavefront
+  wave_forward_quad(A, N, c0, lane, lds + w * kQuadDoubles);
 }
 
 }  // namespace dragexp

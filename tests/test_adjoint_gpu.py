@@ -97,7 +97,7 @@ def test_backward_vs_oracle(ops, dev, orc, name, cells):
 @pytest.mark.parametrize("N", list(range(1, 17)))
 def test_backward_every_n_both_mappings(ops, dev, orc, N):
     from paper_2509_25347_amd import _lib
-    d = _weights(W.make_stiff(N, 300) if N % 2 == 0 else W.make_jittered(N, 300), seed=N)
+    d = _weights(W.make_stiff(N, 301) if N % 2 == 0 else W.make_jittered(N, 301), seed=N)
     maps = [_lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 8 else [])
     try:
         for mp in maps:

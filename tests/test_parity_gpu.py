@@ -107,7 +107,7 @@ def test_forward_parity_default_mapping(ops, dev, orc, name, cells):
 @pytest.mark.parametrize("N", list(range(1, 17)))
 def test_forward_parity_every_n_both_mappings(ops, dev, orc, N):
     from paper_2509_25347_amd import _lib
-    d = W.make_stiff(N, 700) if N % 2 == 0 else W.make_jittered(N, 700)
+    d = W.make_stiff(N, 701) if N % 2 == 0 else W.make_jittered(N, 701)
     ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"])
     maps = [_lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 8 else [])
     try:
