@@ -63,17 +63,21 @@ def algorithmic_bytes(C, N, D):
     return 8.0 * C * (1 + 2 * N + 2 * D * (N + 1))
 
 
-def source_hash():
-    """Short SHA-256 over the HIP sources; a profile summary records the hash
-    of the sources its counters were taken on."""
+KERNEL_SOURCES = {"k_forward_wave": ("common.hpp", "wave.hpp"),
+                  "k_forward_lane": ("common.hpp", "lane.hpp")}
+
+
+def source_hash(kernel):
+    """Short SHA-256 over the sources that define `kernel` and the compiler
+    flags; a profile summary records the hash its counters were taken on."""
     import hashlib
-    h = hashlib.sha256()
+    from paper_2509_25347_amd import _lib
+    h = hashlib.sha256(" ".join(_lib.HIPCC_FLAGS).encode())
     csrc = os.path.join(ROOT, "paper_2509_25347_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -90,7 +94,7 @@ def profiled_traffic(kernel, workload):
             if ":" in line and line.split(":")[0] in ("hbm_bytes_per_launch", "source_sha256"):
                 k, v = line.split(":", 1)
                 fields[k] = v.strip()
-    if fields.get("source_sha256") != source_hash() or "hbm_bytes_per_launch" not in fields:
+    if fields.get("source_sha256") != source_hash(kernel) or "hbm_bytes_per_launch" not in fields:
         return None
     return float(fields["hbm_bytes_per_launch"])
 
@@ -264,7 +268,7 @@ def batched_measurement(torch, ops, workloads, dev):
     fields, v = plan.pack(batch["blocks"], dev)
     out = torch.empty_like(v)
     plan.autotune(fields, v, out)
-    lane_max, persistent = plan.config()
+    lane_max, mfma_mode = plan.config()
     tb = _time(torch, lambda: plan.apply(fields, v, out), 10, 2)
     groups = {}
     for b, blk in enumerate(batch["blocks"]):
@@ -285,7 +289,7 @@ def batched_measurement(torch, ops, workloads, dev):
     return {"workload": "4096 blocks x 512 cells, N_b ~ U{1..16}, D = 3", "n_cells": cells,
             "batched_ms": tb, "plain_per_n_ms": tp, "batched_over_plain": tb / tp,
             "batched_cells_per_s": cells / (tb * 1e-3),
-            "lane_max": lane_max, "persistent_mfma_grid": persistent}
+            "lane_max": lane_max, "mfma_mode": mfma_mode}
 
 
 def extra_measurements(torch, ops, workloads, dev):

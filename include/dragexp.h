@@ -181,11 +181,20 @@ int drag_expm_apply_batched(drag_plan *plan, const double *fields,
 int drag_plan_autotune(drag_plan *plan, const double *fields,
                        const double *v_in, double *v_out,
                        drag_stream_t stream, int32_t *lane_max_out);
-/* The plan's current launch configuration: the lane-mapping bound and
- * whether the MFMA branch runs as a persistent grid over the item queue (1)
- * or as a plain grid over its blocks (0). */
+/* The plan's current launch configuration: the lane-mapping bound and how
+ * the MFMA branch runs: DRAG_MFMA_PERSISTENT (a persistent grid over a work
+ * queue of a few cells per item), DRAG_MFMA_GRID (one plain grid over its
+ * blocks, N at run time) or DRAG_MFMA_PER_N (one plain grid per species
+ * count, each compiled for it).  Either pointer may be NULL. */
+#define DRAG_MFMA_PERSISTENT 0
+#define DRAG_MFMA_GRID 1
+#define DRAG_MFMA_PER_N 2
 int drag_plan_config(const drag_plan *plan, int32_t *lane_max,
-                     int32_t *persistent);
+                     int32_t *mfma_mode);
+/* Pin a launch configuration instead of the tuned one: lane_max in 4..8 and
+ * an mfma_mode above (DRAG_ERR_OPTION otherwise, the plan unchanged).  The
+ * next drag_expm_apply_batched re-captures; results do not depend on it. */
+int drag_plan_set_config(drag_plan *plan, int32_t lane_max, int32_t mfma_mode);
 int drag_plan_destroy(drag_plan *plan);
 
 /* ---- status and introspection -------------------------------------------- */

@@ -53,7 +53,7 @@ MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 EXPORTS = [
     "drag_desc_init", "drag_build", "drag_expm_apply", "drag_expm_apply_backward",
     "drag_plan_batched", "drag_plan_offsets", "drag_expm_apply_batched",
-    "drag_plan_autotune", "drag_plan_config", "drag_plan_destroy", "drag_get_status", "drag_clear_status", "drag_status_string",
+    "drag_plan_autotune", "drag_plan_config", "drag_plan_set_config", "drag_plan_destroy", "drag_get_status", "drag_clear_status", "drag_status_string",
     "drag_table_row", "drag_select", "drag_set_mapping", "drag_get_mapping",
 ]
 
@@ -132,6 +132,8 @@ def lib():
     L.drag_plan_autotune.restype = ctypes.c_int
     L.drag_plan_config.argtypes = [vp, P(i32), P(i32)]
     L.drag_plan_config.restype = ctypes.c_int
+    L.drag_plan_set_config.argtypes = [vp, i32, i32]
+    L.drag_plan_set_config.restype = ctypes.c_int
     L.drag_plan_destroy.argtypes = [vp]
     L.drag_plan_destroy.restype = ctypes.c_int
     L.drag_get_status.argtypes = [vp, P(i32)]

@@ -252,236 +252,274 @@ __global__ void __launch_bounds__(256) k_backward_lane(BackArgs A, int xcd_block
   }
 }
 
-// ---- one cell per wavefront, FP64 MFMA ---------------------------------------------
+// ---- MFMA adjoint, N = 9..16: a quad of cells per wavefront ---------------------
+//
+// The recurrences run on separate 16 x 16 tiles for Y and dY.  As in the
+// forward kernel the B operand of every product comes straight from the D
+// layout and only A operands are staged through LDS; products by B = M^T
+// (diagonal plus rank one: (B X)[r][c] = -b_r X[r][c] - pb_r sum_l X[l][c])
+// run on the vector ALU; a squaring step is
+//     Y' = (Y + 2I) Y,   dY' = dY Y + (Y + 2I) dY,
+// with Y + 2I formed in the staged copy by one LDS add on the diagonal.
 
-__device__ __forceinline__ double group16_sum(double x) {
+__device__ __forceinline__ double groups_sum(double x) { return sum_rows(x); }
+
+// X <- B X for B = M^T (rows >= N stay zero: nb, npb are zero there).
+__device__ __forceinline__ v4d mul_Bt(const v4d& X, const double (&nb)[4], const double (&npb)[4]) {
+  const double cs = sum_rows(X[0] + X[1] + X[2] + X[3]);  // column sums of X
+  v4d Y;
 #pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
+  for (int v = 0; v < 4; ++v) Y[v] = fma(nb[v], X[v], npb[v] * cs);
+  return Y;
 }
 
-__device__ __forceinline__ double groups_sum(double x) {
-  x += __shfl_xor(x, 16, 64);
-  x += __shfl_xor(x, 32, 64);
-  return x;
+// T_m(B) - I and its derivative in the direction dB by the Paterson-Stockmeyer
+// scheme with Q powers: P_p = B P_{p-1} (structured), dP_p = dB P_{p-1} +
+// B dP_{p-1}; Horner F <- Bbar_k + F P_Q, dF <- dBbar_k + dF P_Q + F dP_Q.
+template <int Q>
+__device__ __forceinline__ void bwd_poly(const v4d& Bt, const v4d& dB, const double (&dBA)[4],
+                                         const double (&nb)[4], const double (&npb)[4], int r,
+                                         double* stage, double* stage2, int g, int j, v4d& F,
+                                         v4d& dF) {
+  const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
+  v4d P[Q + 1], dP[Q + 1];
+  P[1] = Bt;
+  dP[1] = dB;
+#pragma unroll
+  for (int p = 2; p <= Q; ++p) {
+    double Bp[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Bp[t] = P[p - 1][t];
+    P[p] = mul_Bt(P[p - 1], nb, npb);
+    dP[p] = mma16(dBA, Bp, mul_Bt(dP[p - 1], nb, npb));
+  }
+  double Bq[4], dBq[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    Bq[t] = P[Q][t];
+    dBq[t] = dP[Q][t];
+  }
+  auto comb = [&](const v4d (&X)[Q + 1], int k) {
+    v4d acc = zero4;
+#pragma unroll
+    for (int p = 1; p <= Q; ++p) {
+      const double cf = kInvFact[Q * k + p];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = fma(cf, X[p][v], acc[v]);
+    }
+    return acc;
+  };
+  F = comb(P, r - 1);
+  dF = comb(dP, r - 1);
+  for (int k = r - 2; k >= 0; --k) {
+    double AF[4], AdF[4];
+    stage_tile(stage, g, j, F);
+    stage_tile(stage2, g, j, dF);
+    load_a_ops(stage, g, j, AF);
+    load_a_ops(stage2, g, j, AdF);
+    dF = mma16(AF, dBq, mma16(AdF, Bq, comb(dP, k)));
+    F = mma16(AF, Bq, comb(P, k));
+  }
 }
 
-template <int N>
-__global__ void __launch_bounds__(256) k_backward_wave(BackArgs A, int xcd_blocks) {
-  __shared__ double lds[4 * 3 * kStageDoubles];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+__device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int N, int64_t c0,
+                                                   int lane, double* lds) {
   const int g = lane >> 4, j = lane & 15;
-  const int bid = blockIdx.x;
-  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
-  const int64_t cell = logical * 4 + w;
-  if (cell >= A.n_cells) return;  // uniform over the wavefront
-  double* bufX = lds + (3 * w) * kStageDoubles;
-  double* bufY = bufX + kStageDoubles;
-  double* bufZ = bufY + kStageDoubles;
   const int64_t ld = A.ld;
   const int n1 = N + 1;
   const int D = A.n_dim;
   const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
+  double* stage = lds;                    // Y (and F) staging
+  double* stage2 = lds + kQuadDoubles;    // dY (and dF, dB) staging
+  double* qa = lds + kStageDoubles;
+  double* qe = qa + 64;
+  double* qp = qe + 64;
 
-  WaveCell Wc;
-  wave_setup(Wc, N, A.rho_g, A.rho_d, A.t_stop, ld, cell, A.dt, A.k_max, A.option, j);
+  const QuadCell Q = quad_setup(A.rho_g, A.rho_d, A.t_stop, A.n_cells, ld, A.dt, A.k_max,
+                                A.option, N, c0, g, j, qa, qe, qp);
+  const int diag_slot = j * kLdsStride + j;
 
-  // velocity data in the component-species layout: lane (g = component c,
-  // j = species) holds the cell's values of component c for species j
-  const bool cj = (g < D) && (j < N);
-  double v0 = 0.0, vj = 0.0, w0 = 0.0, wj = 0.0;
-  bool fin = true;
-  if (g < D) {
-    const int64_t base = (int64_t)(g * n1) * ld + cell;
-    v0 = A.v_in[base];
-    w0 = A.w[base];
-    fin = isfinite(v0) && isfinite(w0);
-    if (j < N) {
-      vj = A.v_in[base + (int64_t)(1 + j) * ld];
-      wj = A.w[base + (int64_t)(1 + j) * ld];
-      fin = fin && isfinite(vj) && isfinite(wj);
-    }
-  }
-  const unsigned bad = Wc.bad | (__all(fin) ? 0u : kBadVelocity);
-  if (bad) {
-    const double qnan = __builtin_nan("");
-    if (lane < D * n1) {
-      if (A.v_out) A.v_out[(int64_t)lane * ld + cell] = qnan;
-      if (A.g_v) A.g_v[(int64_t)lane * ld + cell] = qnan;
-    }
-    if (lane < N) {
-      if (A.g_logt) A.g_logt[lane * ld + cell] = qnan;
-      if (A.g_t) A.g_t[lane * ld + cell] = qnan;
-      if (A.g_rho_d) A.g_rho_d[lane * ld + cell] = qnan;
-    }
-    if (lane == 0) {
-      if (A.g_rho_g) A.g_rho_g[cell] = qnan;
-      atomicOr(&g_status_word, bad);
-    }
-    return;
-  }
-
-  const double Wsum = w0 + group16_sum(cj ? wj : 0.0);  // W_c of this lane's component
-  const double dv = cj ? vj - v0 : 0.0;
-  const double ub = cj ? wj - Wsum * Wc.ej / Wc.sigma : 0.0;
-
-  const int s = Wc.kms.s;
-  const int q = kTabQ[Wc.kms.k], r = kTabR[Wc.kms.k];
-  const double bj = ldexp(Wc.aj, -s), pbj = ldexp(Wc.pj, -s);
-
-  // dB = 2^-s G, G = Ubar dV^T: one MFMA with k = the velocity component
-  v4d dB = __builtin_amdgcn_mfma_f64_16x16x4f64(ub, dv, zero4, 0, 0, 0);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) dB[v] = ldexp(dB[v], -s);
-
-  // B = M^T: B[row][col] = -b_row [row == col] - pb_row
-  v4d Bm;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = 4 * v + g;
-    const double pbr = __shfl(pbj, row, 64);
-    Bm[v] = (row < N && j < N) ? ((row == j ? -bj : 0.0) - pbr) : 0.0;
-  }
-  double BmA[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int col = 4 * t + g;
-    BmA[t] = (j < N && col < N) ? ((j == col ? -bj : 0.0) - pbj) : 0.0;
-  }
-  double dBA[4];
-  stage_tile(bufZ, g, j, dB);
-  load_a_ops(bufZ, g, j, dBA);
-
-  // powers and their derivatives
-  v4d P[6], dP[6];
-  P[1] = Bm;
-  dP[1] = dB;
-#pragma unroll
-  for (int jj = 2; jj <= 5; ++jj) {
-    if (jj <= q) {
-      double Bp[4], Bdp[4];
-      stage_tile(bufX, g, j, P[jj - 1]);
-      stage_tile(bufY, g, j, dP[jj - 1]);
-      load_b_ops(bufX, g, j, Bp);
-      load_b_ops(bufY, g, j, Bdp);
-      P[jj] = mma16(BmA, Bp, zero4);
-      dP[jj] = mma16(dBA, Bp, zero4);
-      dP[jj] = mma16(BmA, Bdp, dP[jj]);
-    } else {
-      P[jj] = zero4;
-      dP[jj] = zero4;
-    }
-  }
-  v4d Pq = P[1], dPq = dP[1];
-#pragma unroll
-  for (int jj = 2; jj <= 5; ++jj)
-    if (jj == q) {
-      Pq = P[jj];
-      dPq = dP[jj];
-    }
-  auto comb = [&](const v4d (&X)[6], int k) {
-    v4d acc = zero4;
-#pragma unroll
-    for (int jj = 1; jj <= 5; ++jj) {
-      if (jj <= q) {
-        const double cf = kInvFact[q * k + jj];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = fma(cf, X[jj][v], acc[v]);
+  // velocity and weight data, lane (g = component, j = species)
+  const bool comp = g < D;
+  const bool cj = comp && j < N;
+  auto load_vw = [&](int64_t cell, double& v0, double& vj, double& w0, double& wj) {
+    v0 = vj = w0 = wj = 0.0;
+    if (comp && cell < A.n_cells) {
+      const int64_t base = (int64_t)(g * n1) * ld + cell;
+      v0 = A.v_in[base];
+      w0 = A.w[base];
+      if (j < N) {
+        vj = A.v_in[base + (int64_t)(1 + j) * ld];
+        wj = A.w[base + (int64_t)(1 + j) * ld];
       }
     }
-    return acc;
   };
+  double v0n, vjn, w0n, wjn;
+  load_vw(c0, v0n, vjn, w0n, wjn);
 
-  // Horner
-  double Bq[4], dBq[4];
-  stage_tile(bufX, g, j, Pq);
-  stage_tile(bufY, g, j, dPq);
-  load_b_ops(bufX, g, j, Bq);
-  load_b_ops(bufY, g, j, dBq);
-  v4d F = comb(P, r - 1), dF = comb(dP, r - 1);
-  for (int k = r - 2; k >= 0; --k) {
-    double AF[4], AdF[4];
-    stage_tile(bufX, g, j, F);
-    stage_tile(bufY, g, j, dF);
-    load_a_ops(bufX, g, j, AF);
-    load_a_ops(bufY, g, j, AdF);
-    const v4d Fn = mma16(AF, Bq, comb(P, k));
-    v4d dFn = mma16(AdF, Bq, comb(dP, k));
-    dF = mma16(AF, dBq, dFn);
-    F = Fn;
-  }
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int64_t cell = c0 + c;
+    if (cell >= A.n_cells) break;  // uniform
+    const double v0 = v0n, vj = vjn, w0 = w0n, wj = wjn;
+    if (c < 3) load_vw(cell + 1, v0n, vjn, w0n, wjn);  // prefetch the next cell
 
-  // squarings with the Frechet recurrence
-  v4d Y = F, dY = dF;
-  for (int it = 0; it < s; ++it) {
-    double AY[4], BY[4], AdY[4], BdY[4];
-    stage_tile(bufX, g, j, Y);
-    stage_tile(bufY, g, j, dY);
-    load_a_ops(bufX, g, j, AY);
-    load_b_ops(bufX, g, j, BY);
-    load_a_ops(bufY, g, j, AdY);
-    load_b_ops(bufY, g, j, BdY);
-    const v4d Yn = mma16(AY, BY, Y + Y);
-    v4d dYn = mma16(AdY, BY, dY + dY);
-    dY = mma16(AY, BdY, dYn);
-    Y = Yn;
-  }
+    unsigned bad = (unsigned)__builtin_amdgcn_readlane((int)Q.bad, 16 * c);
+    const bool fin = isfinite(v0) && isfinite(vj) && isfinite(w0) && isfinite(wj);
+    if (!__all(fin) && !bad) bad = kBadVelocity;
+    if (bad) {
+      const double qnan = __builtin_nan("");
+      if (lane < D * n1) {
+        if (A.v_out) A.v_out[(int64_t)lane * ld + cell] = qnan;
+        if (A.g_v) A.g_v[(int64_t)lane * ld + cell] = qnan;
+      }
+      if (lane < N) {
+        if (A.g_logt) A.g_logt[lane * ld + cell] = qnan;
+        if (A.g_t) A.g_t[lane * ld + cell] = qnan;
+        if (A.g_rho_d) A.g_rho_d[lane * ld + cell] = qnan;
+      }
+      if (lane == 0) {
+        if (A.g_rho_g) A.g_rho_g[cell] = qnan;
+        atomicOr(&g_status_word, bad);
+      }
+      continue;
+    }
+    const int kp = __builtin_amdgcn_readlane(Q.kpack, 16 * c);
+    const int kk = kp & 15, s = kp >> 4;
+    const int q = kTabQ[kk], r = kTabR[kk];
+    const double sigma = readlane_f64(Q.sig, 16 * c);
 
-  // Y = Z^T, dY = dL/dAt.  u_c = Z dv_c = (dV^T Y)[c];  Z^T ubar_c = (Ubar^T Z)[c]
-  double YB[4], ZB[4], DvA[4], UbA[4];
-  stage_tile(bufX, g, j, Y);
-  load_b_ops(bufX, g, j, YB);   // Y as the B operand
-  load_a_ops(bufX, g, j, ZB);   // Z = Y^T as the B operand
+    const int sj = 16 * c + quad_slot(j);
+    const double ej = qe[sj], aj = qa[sj], nbj = -ldexp(aj, -s);
+    double nb[4], npb[4];  // -b, -pb of rows 4 v + g
+    {
+      const double* ra = qa + 16 * c + 4 * g;
+      const double* rp = qp + 16 * c + 4 * g;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    // A operand rows are components: lane (g, i) takes component i, species 4t+g
-    const int src = (j < D) ? 16 * j + 4 * t + g : 0;
-    const double a1 = __shfl(dv, src, 64), a2 = __shfl(ub, src, 64);
-    DvA[t] = (j < D) ? a1 : 0.0;
-    UbA[t] = (j < D) ? a2 : 0.0;
-  }
-  const v4d Um = mma16(DvA, YB, zero4);   // lane (g, j) [0]: u_g[j]
-  const v4d Vm = mma16(UbA, ZB, zero4);   // lane (g, j) [0]: (Z^T ubar_g)_j
-  const double u = cj ? Um[0] : 0.0;
-  const double zt = cj ? Vm[0] : 0.0;
-  const double eu = group16_sum(Wc.ej * u);
-  const double d0 = -eu / Wc.sigma;
-  const double zt_sum = group16_sum(zt);
-  if (g < D) {
-    const int64_t base = (int64_t)(g * n1) * ld + cell;
-    if (A.v_out) {
-      if (j < N) A.v_out[base + (int64_t)(1 + j) * ld] = vj + (d0 + u);
-      if (j == 0) A.v_out[base] = v0 + d0;
+      for (int v = 0; v < 4; ++v) {
+        nb[v] = -ldexp(ra[v], -s);
+        npb[v] = -ldexp(rp[v], -s);
+      }
     }
-    if (A.g_v) {
-      if (j < N) A.g_v[base + (int64_t)(1 + j) * ld] = wj + zt;
-      if (j == 0) A.g_v[base] = w0 - zt_sum;
-    }
-  }
-  // direct dependence of the gas update on e, summed over components
-  const double ge_dir = groups_sum(cj ? (-d0 - u) * (Wsum / Wc.sigma) : 0.0);
-  // column sums and diagonal of dL/dAt (D layout: rows 4v+g of column j)
-  double col = dY[0] + dY[1] + dY[2] + dY[3];
-  col = groups_sum(col);
-  double dg = 0.0;
+    __builtin_amdgcn_wave_barrier();
+
+    const double Wsum = row_chain(w0, cj ? wj : 0.0, N);  // W_c of this lane's component
+    const double dv = cj ? vj - v0 : 0.0;
+    const double ub = cj ? wj - Wsum * ej / sigma : 0.0;
+
+    // dB = 2^-s G, G = Ubar dV^T: one MFMA with k = the velocity component
+    v4d dB = __builtin_amdgcn_mfma_f64_16x16x4f64(ub, dv, zero4, 0, 0, 0);
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
-    if (4 * v + g == j) dg = dY[v];
-  dg = groups_sum(dg);
-  if (g == 0) {
-    const double rg = A.rho_g[cell];
-    double ge = 0.0;
-    if (j < N) {
-      const double ga = -dg - Wc.ej * col;
-      ge = -Wc.aj * col + ge_dir;
-      const double glt = -Wc.aj * ga;
-      if (A.g_logt) A.g_logt[j * ld + cell] = glt;
-      if (A.g_t) A.g_t[j * ld + cell] = glt / A.t_stop[j * ld + cell];
-      if (A.g_rho_d) A.g_rho_d[j * ld + cell] = ge / rg;
+    for (int v = 0; v < 4; ++v) dB[v] = ldexp(dB[v], -s);
+    double dBA[4];
+    stage_tile(stage2, g, j, dB);
+    load_a_ops(stage2, g, j, dBA);
+
+    // B = M^T: B[row][col] = -b_row [row == col] - pb_row
+    v4d Bt;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double dg = (4 * v + g == j) ? 1.0 : 0.0;
+      Bt[v] = (j < N) ? fma(dg, nbj, npb[v]) : 0.0;
     }
-    const double sum_ege = group16_sum(Wc.ej * ge);
-    if (j == 0 && A.g_rho_g) A.g_rho_g[cell] = -sum_ege / rg;
+    v4d F, dF;
+    switch (q) {  // uniform; one code path per power count
+      case 1: bwd_poly<1>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+      case 2: bwd_poly<2>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+      case 3: bwd_poly<3>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+      case 4: bwd_poly<4>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+      default: bwd_poly<5>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+    }
+
+    // squarings with the Frechet recurrence
+    v4d Y = F, dY = dF;
+    for (int it = 0; it < s; ++it) {
+      double AY[4], AdY[4], BY[4], BdY[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        BY[t] = Y[t];
+        BdY[t] = dY[t];
+      }
+      stage_tile(stage, g, j, Y);
+      stage_tile(stage2, g, j, dY);
+      if (g == 0) atomicAdd(stage + diag_slot, 2.0);
+      __builtin_amdgcn_wave_barrier();
+      load_a_ops(stage, g, j, AY);    // Y + 2I
+      load_a_ops(stage2, g, j, AdY);  // dY
+      dY = mma16(AdY, BY, mma16(AY, BdY, zero4));
+      Y = mma16(AY, BY, zero4);
+    }
+
+    // Y = Z^T, dY = dL/dAt.  u_c = Z dv_c = (dV^T Y)[c];  Z^T ubar_c = (Ubar^T Z)[c]
+    double YB[4], ZB[4], DvA[4], UbA[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) YB[t] = Y[t];
+    stage_tile(stage, g, j, Y);
+    load_a_ops(stage, g, j, ZB);  // Z = Y^T as the B operand
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      // A operand rows are components: lane (g, i) takes component i, species 4t+g
+      const int src = (j < D) ? 16 * j + 4 * t + g : 0;
+      const double a1 = __shfl(dv, src, 64), a2 = __shfl(ub, src, 64);
+      DvA[t] = (j < D) ? a1 : 0.0;
+      UbA[t] = (j < D) ? a2 : 0.0;
+    }
+    const v4d Um = mma16(DvA, YB, zero4);  // lane (g, j) [0]: u_g[j]
+    const v4d Vm = mma16(UbA, ZB, zero4);  // lane (g, j) [0]: (Z^T ubar_g)_j
+    const double u = cj ? Um[0] : 0.0;
+    const double zt = cj ? Vm[0] : 0.0;
+    const double eu = row_chain(0.0, ej * u, N);
+    const double d0 = -eu / sigma;
+    const double zt_sum = row_chain(0.0, zt, N);
+    if (comp) {
+      const int64_t base = (int64_t)(g * n1) * ld + cell;
+      if (A.v_out) {
+        if (j < N) A.v_out[base + (int64_t)(1 + j) * ld] = vj + (d0 + u);
+        if (j == 0) A.v_out[base] = v0 + d0;
+      }
+      if (A.g_v) {
+        if (j < N) A.g_v[base + (int64_t)(1 + j) * ld] = wj + zt;
+        if (j == 0) A.g_v[base] = w0 - zt_sum;
+      }
+    }
+    // direct dependence of the gas update on e, summed over components
+    const double ge_dir = groups_sum(cj ? (-d0 - u) * (Wsum / sigma) : 0.0);
+    // column sums and diagonal of dL/dAt (D layout: rows 4v+g of column j)
+    const double col = groups_sum(dY[0] + dY[1] + dY[2] + dY[3]);
+    double dg = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (4 * v + g == j) dg = dY[v];
+    dg = groups_sum(dg);
+    if (g == 0) {
+      const double rg = A.rho_g[cell];
+      double ge = 0.0;
+      if (j < N) {
+        const double ga = -dg - ej * col;
+        ge = -aj * col + ge_dir;
+        const double glt = -aj * ga;
+        if (A.g_logt) A.g_logt[j * ld + cell] = glt;
+        if (A.g_t) A.g_t[j * ld + cell] = glt / A.t_stop[j * ld + cell];
+        if (A.g_rho_d) A.g_rho_d[j * ld + cell] = ge / rg;
+      }
+      const double sum_ege = row_chain(0.0, ej * ge, N);
+      if (j == 0 && A.g_rho_g) A.g_rho_g[cell] = -sum_ege / rg;
+    }
   }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_backward_wave(BackArgs A, int xcd_blocks) {
+  // per wavefront: the quad block (staging tile + coefficient tables) and a
+  // second staging tile
+  __shared__ double lds[4 * (kQuadDoubles + kStageDoubles)];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int64_t c0 = (logical * 4 + w) * 4;
+  if (c0 >= A.n_cells) return;  // uniform over the wavefront
+  wave_backward_quad(A, N, c0, lane, lds + w * (kQuadDoubles + kStageDoubles));
 }
 
 // ---- N <= 8: the block form on one 16 x 16 tile -------------------------------

@@ -1,12 +1,13 @@
 // batched.hpp -- AMR-style blocks with uneven species counts N_b in [1, 16],
 // all updated by one hipGraph launch.
 //
-// Blocks are split by mapping.  Blocks with N_b > LMAX go to one persistent
-// MFMA grid (one cell per wavefront, N taken at run time, so a single code
-// path serves N = LMAX+1..16): the plan cuts them into work items of a few
-// cells, and every wavefront of the persistent grid takes the next item from
-// a device counter with one atomic add until the queue is empty, so blocks
-// of uneven cost balance themselves.  Blocks with N_b <= LMAX run one cell
+// Blocks are split by mapping.  Blocks with N_b > LMAX run on the MFMA path
+// (a quad of cells per wavefront) in one of three forms the autotuner picks
+// from: a persistent grid (N taken at run time, so a single code path serves
+// N = LMAX+1..16) whose wavefronts take work items of a few cells from a
+// device counter with one atomic add until the queue is empty, so blocks of
+// uneven cost balance themselves; one plain grid over those blocks (N at run
+// time); or one plain grid per N, each compiled for its N.  Blocks with N_b <= LMAX run one cell
 // per lane in one grid per N (one 64-cell item per wavefront), each compiled
 // with exactly the registers its N needs.  The plan captures all of them
 // into one graph whose lane and MFMA branches are independent, so they can
@@ -88,8 +89,11 @@ __global__ void __launch_bounds__(256) k_batched_wave(BatchArgs B) {
 // The same MFMA work as a plain grid: workgroup w takes 16 consecutive cells
 // of one wave-mapped block (a quad per wavefront).  No loop, so none of the
 // loop-invariant state the persistent grid keeps live across items; the
-// hardware dispatcher balances the workgroups.  The autotuner picks between
-// the two.
+// hardware dispatcher balances the workgroups.  NC = 0 serves every N (taken
+// from the item at run time); NC > 0 is a grid over the blocks of that one N,
+// compiled for it like the plain per-N kernels.  The autotuner picks among
+// the persistent grid, one run-time-N grid and the per-N grids.
+template <int NC>
 __global__ void __launch_bounds__(256) k_batched_wave_grid(BatchArgs B, int groups_per_block,
                                                            int xcd_blocks) {
   __shared__ double lds[4 * kQuadDoubles];
@@ -103,7 +107,7 @@ __global__ void __launch_bounds__(256) k_batched_wave_grid(BatchArgs B, int grou
   if (item >= B.n_items || c0 >= B.block_cells) return;  // uniform over the wavefront
   const BatchItem it = B.items[item];  // one whole block
   const CellArgs A = block_args(B, it);
-  wave_forward_quad(A, it.n, c0, lane, lds + w * kQuadDoubles);
+  wave_forward_quad(A, NC > 0 ? NC : it.n, c0, lane, lds + w * kQuadDoubles);
 }
 
 // One 64-cell lane item per wavefront, all items of one species count N.

@@ -183,12 +183,14 @@ static int g_default_map[16] = {
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
 static int g_map_override[16] = {0};
 
-// Default mapping of the adjoint.  It keeps three N x N matrices per lane;
-// at N = 8 the lane kernel spills, yet measured on MI355X it still beats the
-// MFMA kernel (whose 16 x 16 tile is 7/8 padding at N = 8).
+// Default mapping of the adjoint.  The lane kernel keeps three N x N
+// matrices per lane and spills at N = 8; there the MFMA block form (Y and dY
+// on one 16 x 16 tile, one product per squaring) is faster (measured on
+// MI355X, 2^18 stiff cells: lane 1.68 ms, block 1.21 ms), while for N <= 7
+// the lane kernel wins.
 static int g_default_map_bwd[16] = {
     DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
-    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
+    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_WAVE,
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
 
@@ -243,10 +245,12 @@ static bool overlap(Range a, Range b) {
 constexpr int kBatchVariants = 5;
 constexpr int kBatchLmax[kBatchVariants] = {4, 5, 6, 7, 8};
 constexpr int kWaveItemCells = 8;
-// how the MFMA branch runs: a persistent grid over the item queue, or a
-// plain grid over the blocks
+// how the MFMA branch runs: a persistent grid over the item queue, a plain
+// grid over the blocks (N at run time), or one plain grid per N
 constexpr int kWavePersistent = 0;
 constexpr int kWaveGrid = 1;
+constexpr int kWavePerN = 2;
+constexpr int kWaveModes = 3;
 
 struct BatchVariant {
   int lmax = 6;
@@ -254,6 +258,8 @@ struct BatchVariant {
   int n_wave = 0;
   BatchItem* d_wave_blocks = nullptr;  // the same blocks whole, for the plain grid
   int n_wave_blocks = 0;
+  BatchItem* d_wave_n[kMaxSpecies + 1] = {};  // the same blocks whole, per N
+  int n_wave_n[kMaxSpecies + 1] = {};
   BatchItem* d_lane[kLaneMaxN + 1] = {};  // 64-cell lane items per N <= lmax
   int n_lane[kLaneMaxN + 1] = {};
 };
@@ -261,6 +267,31 @@ struct BatchVariant {
 template <int N>
 static void launch_batched_lane(const BatchArgs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_batched_lane<N>, dim3((B.n_items + 3) / 4), dim3(256), 0, st, B);
+}
+
+template <int N>
+static void launch_batched_wave_n(const BatchArgs& B, int gpb, hipStream_t st) {
+  const Grid gr = grid_for((int64_t)B.n_items * gpb);
+  hipLaunchKernelGGL(k_batched_wave_grid<N>, dim3(gr.blocks), dim3(256), 0, st, B, gpb,
+                     gr.xcd_blocks);
+}
+
+// N = 5..16: the species counts the MFMA branch can hold (LMAX >= 4)
+static void batched_wave_n(int N, const BatchArgs& B, int gpb, hipStream_t st) {
+  switch (N) {
+    case 5: launch_batched_wave_n<5>(B, gpb, st); break;
+    case 6: launch_batched_wave_n<6>(B, gpb, st); break;
+    case 7: launch_batched_wave_n<7>(B, gpb, st); break;
+    case 8: launch_batched_wave_n<8>(B, gpb, st); break;
+    case 9: launch_batched_wave_n<9>(B, gpb, st); break;
+    case 10: launch_batched_wave_n<10>(B, gpb, st); break;
+    case 11: launch_batched_wave_n<11>(B, gpb, st); break;
+    case 12: launch_batched_wave_n<12>(B, gpb, st); break;
+    case 13: launch_batched_wave_n<13>(B, gpb, st); break;
+    case 14: launch_batched_wave_n<14>(B, gpb, st); break;
+    case 15: launch_batched_wave_n<15>(B, gpb, st); break;
+    default: launch_batched_wave_n<16>(B, gpb, st); break;
+  }
 }
 
 static void batched_lane(int N, const BatchArgs& B, hipStream_t st) {
@@ -325,6 +356,8 @@ static void plan_free(drag_plan* P) {
   for (BatchVariant& V : P->var) {
     if (V.d_wave) (void)hipFree(V.d_wave);
     if (V.d_wave_blocks) (void)hipFree(V.d_wave_blocks);
+    for (BatchItem* p : V.d_wave_n)
+      if (p) (void)hipFree(p);
     for (BatchItem* p : V.d_lane)
       if (p) (void)hipFree(p);
   }
@@ -369,11 +402,14 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
     BatchVariant& V = P->var[v];
     V.lmax = kBatchLmax[v];
     std::vector<BatchItem> wave, wave_blocks;
-    std::vector<BatchItem> lane[kLaneMaxN + 1];
+    std::vector<BatchItem> lane[kLaneMaxN + 1], wave_n[kMaxSpecies + 1];
     for (int b = 0; b < P->n_blocks; ++b) {
       const int n = P->n_species[b];
       const bool is_lane = n <= V.lmax;
-      if (!is_lane) wave_blocks.push_back(BatchItem{b, n, 0, P->block_cells});
+      if (!is_lane) {
+        wave_blocks.push_back(BatchItem{b, n, 0, P->block_cells});
+        wave_n[n].push_back(BatchItem{b, n, 0, P->block_cells});
+      }
       const int step = is_lane ? 64 : kWaveItemCells;
       for (int first = 0; first < P->block_cells; first += step) {
         const BatchItem it{b, n, first, std::min(step, P->block_cells - first)};
@@ -388,6 +424,10 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
     for (int n = 1; n <= kLaneMaxN && !rc; ++n) {
       V.n_lane[n] = (int)lane[n].size();
       rc = upload(&V.d_lane[n], lane[n]);
+    }
+    for (int n = 1; n <= kMaxSpecies && !rc; ++n) {
+      V.n_wave_n[n] = (int)wave_n[n].size();
+      rc = upload(&V.d_wave_n[n], wave_n[n]);
     }
     if (rc) return rc;
   }
@@ -442,14 +482,23 @@ static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
     W.n_items = V.n_wave;
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, main, P->d_counter);
     hipLaunchKernelGGL(k_batched_wave, dim3(P->wave_grid), dim3(256), 0, main, W);
-  } else if (V.n_wave > 0) {
+  } else if (V.n_wave > 0 && mode == kWaveGrid) {
     BatchArgs W = B;
     W.items = V.d_wave_blocks;
     W.n_items = V.n_wave_blocks;
     const int gpb = (P->block_cells + 15) / 16;
     const Grid gr = grid_for((int64_t)V.n_wave_blocks * gpb);
-    hipLaunchKernelGGL(k_batched_wave_grid, dim3(gr.blocks), dim3(256), 0, main, W, gpb,
+    hipLaunchKernelGGL(k_batched_wave_grid<0>, dim3(gr.blocks), dim3(256), 0, main, W, gpb,
                        gr.xcd_blocks);
+  } else if (V.n_wave > 0) {
+    const int gpb = (P->block_cells + 15) / 16;
+    for (int n = kMaxSpecies; n > lmax; --n) {  // largest N (longest blocks) first
+      if (V.n_wave_n[n] == 0) continue;
+      BatchArgs W = B;
+      W.items = V.d_wave_n[n];
+      W.n_items = V.n_wave_n[n];
+      batched_wave_n(n, W, gpb, main);
+    }
   }
   if (hipStreamWaitEvent(main, P->ev_join, 0) != hipSuccess) return DRAG_ERR_HIP;
   return hip_status(hipGetLastError());
@@ -644,7 +693,7 @@ int drag_plan_autotune(drag_plan* P, const double* fields, const double* v_in, d
   float best_ms = 0.0f;
   int best = P->lmax, best_mode = P->wave_mode, rc = DRAG_OK;
   bool have = false;
-  for (int mode = 0; mode < 2 && rc == DRAG_OK; ++mode) {
+  for (int mode = 0; mode < kWaveModes && rc == DRAG_OK; ++mode) {
     for (int v = 0; v < kBatchVariants && rc == DRAG_OK; ++v) {
       rc = plan_capture(P, kBatchLmax[v], mode, fields, v_in, v_out);
       float ms = 0.0f;
@@ -675,10 +724,20 @@ int drag_plan_autotune(drag_plan* P, const double* fields, const double* v_in, d
   return DRAG_OK;
 }
 
-int drag_plan_config(const drag_plan* P, int32_t* lane_max, int32_t* persistent) {
+int drag_plan_config(const drag_plan* P, int32_t* lane_max, int32_t* mfma_mode) {
   if (!P) return DRAG_ERR_PLAN;
   if (lane_max) *lane_max = P->lmax;
-  if (persistent) *persistent = P->wave_mode == kWavePersistent ? 1 : 0;
+  if (mfma_mode) *mfma_mode = P->wave_mode;
+  return DRAG_OK;
+}
+
+int drag_plan_set_config(drag_plan* P, int32_t lane_max, int32_t mfma_mode) {
+  if (!P) return DRAG_ERR_PLAN;
+  bool known = false;
+  for (int v = 0; v < kBatchVariants; ++v) known = known || kBatchLmax[v] == lane_max;
+  if (!known || mfma_mode < 0 || mfma_mode >= kWaveModes) return DRAG_ERR_OPTION;
+  P->lmax = lane_max;
+  P->wave_mode = mfma_mode;
   return DRAG_OK;
 }
 

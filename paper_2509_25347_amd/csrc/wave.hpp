@@ -13,9 +13,10 @@
 //   B operand (4 x 16, step t):  B[4t + g][j]
 //   C / D (16 x 16, 4 values):   D[4v + g][j], v = 0..3 (rows interleaved
 //                                 across the four lane groups)
-// Products re-distribute the D layout into the A and B layouts through a
-// 16 x 17 LDS tile per operand (the pad column keeps the transposed reads
-// of the A operand free of bank conflicts).
+// The D layout is the B layout (register t of lane 16 g + j holds row 4 t + g,
+// column j), so a product's B operand comes straight from registers; the A
+// operand (the transpose of that pattern) is re-laid through a 16 x 17 LDS
+// tile (the pad column keeps the transposed reads free of bank conflicts).
 #pragma once
 
 #include "common.hpp"
@@ -34,12 +35,6 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ unsigned wave_or_u32(unsigned x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x |= (unsigned)__shfl_xor((int)x, off, 64);
-  return x;
-}
-
 __device__ __forceinline__ void stage_tile(double* buf, int g, int j, const v4d& X) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) buf[(4 * v + g) * kLdsStride + j] = X[v];
@@ -52,68 +47,11 @@ __device__ __forceinline__ void load_a_ops(const double* buf, int g, int i, doub
   __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ void load_b_ops(const double* buf, int g, int j, double (&B)[4]) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t) B[t] = buf[(4 * t + g) * kLdsStride + j];
-  __builtin_amdgcn_wave_barrier();
-}
-
 // D = A B + C over k = 16.
 __device__ __forceinline__ v4d mma16(const double (&A)[4], const double (&B)[4], v4d acc) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], B[t], acc, 0, 0, 0);
   return acc;
-}
-
-// Per-cell set-up of the MFMA adjoint: the lane with j = lane % 16 < N owns
-// species j.  Every lane computes the norm's sums in ascending species
-// order from broadcast values, so ||A||_1 is the same bits as the
-// definition.  Returns the bad-input bits (uniform over the wavefront).
-// N is a run-time argument throughout the MFMA path (it only bounds loops
-// and masks the padded rows and columns of the 16 x 16 tile); the per-N
-// kernels pass a constant and the compiler folds it.
-struct WaveCell {
-  double aj, ej, pj;  // species j = lane % 16 (0 for j >= N)
-  double sigma, nrm;
-  unsigned bad;
-  Kms kms;
-};
-
-__device__ __forceinline__ void wave_setup(WaveCell& W, const int N, const double* rho_g,
-                                           const double* rho_d, const double* t_stop,
-                                           int64_t ld, int64_t cell, double dt, int K,
-                                           int option, int j) {
-  const double rg = rho_g[cell];
-  unsigned bad = gas_bad(rg);
-  W.aj = W.ej = W.pj = 0.0;
-  if (j < N) {
-    const double t = t_stop[j * ld + cell];
-    const double r = rho_d[j * ld + cell];
-    bad |= species_bad(t, r);
-    const Species sp = species_coeffs(dt, t, r, rg);
-    W.aj = sp.a;
-    W.ej = sp.e;
-    W.pj = sp.p;
-  }
-  const bool fin_j = isfinite(W.aj) && isfinite(W.pj);
-  bad = wave_or_u32(bad);
-  double s = 0.0, sig = 1.0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    s = s + readlane_f64(W.pj, i);
-    sig = sig + readlane_f64(W.ej, i);
-  }
-  double nrm = s;
-#pragma unroll
-  for (int i = 0; i < N; ++i) nrm = nrm + readlane_f64(W.aj, i);
-#pragma unroll
-  for (int i = 0; i < N; ++i) nrm = fmax(nrm, readlane_f64(W.pj, i) + readlane_f64(W.aj, i));
-  const bool all_fin = __all(fin_j) && isfinite(nrm);
-  if (!bad && !all_fin) bad |= kBadNorm;
-  W.bad = bad;
-  W.sigma = sig;
-  W.nrm = nrm;
-  W.kms = bad ? Kms{1, 2, 0} : select_kms(nrm, K, option);
 }
 
 // ---- the forward update: four cells per wavefront ---------------------------

@@ -263,12 +263,23 @@ class BatchPlan:
                                                  ctypes.byref(lm)), "drag_plan_autotune")
         return lm.value
 
+    MFMA_MODES = {0: "persistent", 1: "grid", 2: "per_n"}
+
     def config(self):
-        """(lane_max, persistent) of the current launch configuration."""
-        lm, pe = ctypes.c_int32(), ctypes.c_int32()
-        _lib.check(_lib.lib().drag_plan_config(self._plan, ctypes.byref(lm), ctypes.byref(pe)),
+        """(lane_max, mfma_mode) of the current launch configuration; the mode
+        is "persistent", "grid" or "per_n" (drag_plan_config)."""
+        lm, mm = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.lib().drag_plan_config(self._plan, ctypes.byref(lm), ctypes.byref(mm)),
                    "drag_plan_config")
-        return lm.value, bool(pe.value)
+        return lm.value, self.MFMA_MODES[mm.value]
+
+    def set_config(self, lane_max, mfma_mode):
+        """Pin (lane_max, mfma_mode) instead of the tuned configuration
+        (drag_plan_set_config); mfma_mode is a key or value of MFMA_MODES."""
+        if isinstance(mfma_mode, str):
+            mfma_mode = {v: k for k, v in self.MFMA_MODES.items()}[mfma_mode]
+        _lib.check(_lib.lib().drag_plan_set_config(self._plan, int(lane_max), int(mfma_mode)),
+                   "drag_plan_set_config")
 
     def close(self):
         if getattr(self, "_plan", None) is not None and self._plan.value:

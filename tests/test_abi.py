@@ -132,6 +132,7 @@ def test_batched_plan_argument_errors(L):
     assert L.drag_expm_apply_batched(None, None, None, None, None) == _lib.ERR_PLAN
     assert L.drag_plan_offsets(None, None, None, None, None) == _lib.ERR_PLAN
     assert L.drag_plan_config(None, None, None) == _lib.ERR_PLAN
+    assert L.drag_plan_set_config(None, 6, 0) == _lib.ERR_PLAN
     assert L.drag_plan_destroy(None) == _lib.OK
 
 

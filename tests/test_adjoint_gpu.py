@@ -221,3 +221,17 @@ def test_backward_bad_cells(ops, dev, orc, mapping):
     good = [c for c in range(256) if c not in (3, 5, 9)]
     for x in got:
         assert np.isfinite(x[..., good]).all()
+
+
+@pytest.mark.parametrize("N", [2, 8, 12])
+def test_backward_short_quads(ops, dev, orc, N):
+    """MFMA adjoints (block form for N <= 8) on 1..7 cells: quads cut short."""
+    from paper_2509_25347_amd import _lib
+    try:
+        _lib.set_mapping(N, _lib.MAP_WAVE)
+        for C in (1, 3, 5, 7):
+            d = _weights(W.make_stiff(N, C), seed=C)
+            got = gpu_backward(ops, d, dev)
+            check_vs_oracle(orc, d, got, 1e-9, f"N={N} C={C}")
+    finally:
+        _lib.set_mapping(N, _lib.MAP_AUTO)

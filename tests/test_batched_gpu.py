@@ -68,17 +68,30 @@ def test_batched_matches_plain_and_oracle(ops, dev, orc):
 
 
 def test_autotune_and_every_variant_result(ops, dev):
+    """The tuned configuration and every pinned one (lane bound 4..8 x the
+    three MFMA forms) give the plain per-block result bit for bit."""
     batch = W.make_batched(n_blocks=64, block_cells=70, seed_cfg=43)
     plan = ops.BatchPlan(batch["n_species"], 70, 3, batch["dt"])
     fields, v = plan.pack(batch["blocks"], dev)
     out = torch.empty_like(v)
     lm = plan.autotune(fields, v, out)
     assert 4 <= lm <= 8
+    assert plan.config()[1] in ("persistent", "grid", "per_n")
     out2 = plan.apply(fields, v)
     torch.cuda.synchronize()
-    ref = plain_per_block(ops, batch, dev, lane_max=lm)
+    refs = {lm: plain_per_block(ops, batch, dev, lane_max=lm)}
     for b in range(len(batch["blocks"])):
-        assert np.array_equal(plan.block_view(out2, b).cpu().numpy(), ref[b]), b
+        assert np.array_equal(plan.block_view(out2, b).cpu().numpy(), refs[lm][b]), b
+    for lmax in range(4, 9):
+        if lmax not in refs:
+            refs[lmax] = plain_per_block(ops, batch, dev, lane_max=lmax)
+        for mode in ("persistent", "grid", "per_n"):
+            plan.set_config(lmax, mode)
+            assert plan.config() == (lmax, mode)
+            o = plan.apply(fields, v)
+            torch.cuda.synchronize()
+            for b in range(len(batch["blocks"])):
+                assert np.array_equal(plan.block_view(o, b).cpu().numpy(), refs[lmax][b]), (lmax, mode, b)
     plan.close()
 
 

@@ -244,3 +244,50 @@ def test_bad_cells(ops, dev, orc, mapping):
     assert (e <= np.maximum(4 * U * nrm[good], 1e-13)).all()
     # the decoupled species (t = inf) keeps its velocity up to rounding
     assert np.abs(got[:, 4, 6] - v[:, 4, 6]).max() <= 1e-13 * np.abs(v[:, :, 6]).max()
+
+
+@pytest.mark.parametrize("N", [3, 9, 16])
+def test_wave_short_quads_and_ld(ops, dev, orc, N):
+    """The MFMA kernel takes cells four at a time: quads cut short (1..7 cells)
+    and a leading dimension past the last cell (padding never read)."""
+    from paper_2509_25347_amd import _lib
+    try:
+        _lib.set_mapping(N, _lib.MAP_WAVE)
+        for C in (1, 2, 3, 5, 6, 7):
+            d = W.make_stiff(N, C)
+            ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"])
+            got = run(ops, d, dev)
+            assert_parity(got, ref, nrm, d, f"N={N} C={C}")
+            ld = C + 5
+            big = {k: np.full(d[k].shape[:-1] + (ld,), np.nan) for k in ("rho_d", "t_stop", "v")}
+            for k in big:
+                big[k][..., :C] = d[k]
+            Tb = {k: torch.from_numpy(big[k]).to(dev)[..., :C] for k in big}
+            out_full = torch.full(big["v"].shape, 7.0, dtype=torch.float64, device=dev)
+            ops.expm_apply(torch.from_numpy(d["rho_g"]).to(dev), Tb["rho_d"], Tb["t_stop"],
+                           Tb["v"], d["dt"], out=out_full[..., :C])
+            torch.cuda.synchronize()
+            assert_parity(out_full[..., :C].cpu().numpy(), ref, nrm, d, f"N={N} C={C} ld")
+            assert (out_full[..., C:] == 7.0).all()
+    finally:
+        _lib.set_mapping(N, _lib.MAP_AUTO)
+
+
+def test_wave_bad_cells_inside_quads(ops, dev, orc):
+    """Bad cells next to good ones in the same quad of the N = 16 kernel."""
+    d = W.make("n16_stiff_3d", 64)
+    rg, rd, ts, v = (d[k].copy() for k in ("rho_g", "rho_d", "t_stop", "v"))
+    rg[1] = -1.0
+    ts[15, 6] = 0.0
+    v[2, 16, 9] = np.nan
+    rd[3, 12] = np.inf
+    ref, kms, nrm, st = orc.apply_cells(rg, rd, ts, v, 1.0)
+    ops.clear_status()
+    got = run(ops, dict(rho_g=rg, rho_d=rd, t_stop=ts, v=v, dt=1.0), dev)
+    assert ops.get_status() == st
+    badc = (1, 6, 9, 12)
+    for c in badc:
+        assert np.isnan(got[:, :, c]).all(), c
+    good = np.array([c for c in range(64) if c not in badc])
+    e = cell_errors(got[..., good], ref[..., good], v[..., good])
+    assert (e <= np.maximum(4 * U * nrm[good], 1e-13)).all()
