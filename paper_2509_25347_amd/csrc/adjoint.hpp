@@ -128,21 +128,25 @@ __global__ void __launch_bounds__(256) k_backward_lane(BackArgs A, int xcd_block
     }
   }
 
-  // squarings with the Frechet recurrence
+  // squarings with the Frechet recurrence, the 2 Y and 2 dY terms folded
+  // into the right factor Y + 2 I:
+  //   dY <- dY (Y + 2I) + Y dY,   Y <- Y (Y + 2I)
   const int s_max = wave_max_int(s);
   for (int it = 0; it < s_max; ++it) {
     if (it < s) {
+      double d2[N];
+#pragma unroll
+      for (int l = 0; l < N; ++l) d2[l] = Y[l][l] + 2.0;
       double T[N][N];
 #pragma unroll
       for (int i = 0; i < N; ++i)
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-          double acc = 2.0 * dY[i][k];
+          double acc = dY[i][0] * (k == 0 ? d2[0] : Y[0][k]);
 #pragma unroll
-          for (int l = 0; l < N; ++l) {
-            acc = fma(dY[i][l], Y[l][k], acc);
-            acc = fma(Y[i][l], dY[l][k], acc);
-          }
+          for (int l = 1; l < N; ++l) acc = fma(dY[i][l], l == k ? d2[l] : Y[l][k], acc);
+#pragma unroll
+          for (int l = 0; l < N; ++l) acc = fma(Y[i][l], dY[l][k], acc);
           T[i][k] = acc;
         }
 #pragma unroll
@@ -153,9 +157,9 @@ __global__ void __launch_bounds__(256) k_backward_lane(BackArgs A, int xcd_block
       for (int i = 0; i < N; ++i)
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-          double acc = 2.0 * Y[i][k];
+          double acc = Y[i][0] * (k == 0 ? d2[0] : Y[0][k]);
 #pragma unroll
-          for (int l = 0; l < N; ++l) acc = fma(Y[i][l], Y[l][k], acc);
+          for (int l = 1; l < N; ++l) acc = fma(Y[i][l], l == k ? d2[l] : Y[l][k], acc);
           T[i][k] = acc;
         }
 #pragma unroll
@@ -337,6 +341,7 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
 
   const QuadCell Q = quad_setup(A.rho_g, A.rho_d, A.t_stop, A.n_cells, ld, A.dt, A.k_max,
                                 A.option, N, c0, g, j, qa, qe, qp);
+  const double rsig_q = 1.0 / Q.sig;  // 1 / sigma of the row's cell
   const int diag_slot = j * kLdsStride + j;
 
   // velocity and weight data, lane (g = component, j = species)
@@ -387,7 +392,7 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
     const int kp = __builtin_amdgcn_readlane(Q.kpack, 16 * c);
     const int kk = kp & 15, s = kp >> 4;
     const int q = kTabQ[kk], r = kTabR[kk];
-    const double sigma = readlane_f64(Q.sig, 16 * c);
+    const double rsig = readlane_f64(rsig_q, 16 * c);
 
     const int sj = 16 * c + quad_slot(j);
     const double ej = qe[sj], aj = qa[sj], nbj = -ldexp(aj, -s);
@@ -405,7 +410,7 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
 
     const double Wsum = row_chain(w0, cj ? wj : 0.0, N);  // W_c of this lane's component
     const double dv = cj ? vj - v0 : 0.0;
-    const double ub = cj ? wj - Wsum * ej / sigma : 0.0;
+    const double ub = cj ? wj - Wsum * ej * rsig : 0.0;
 
     // dB = 2^-s G, G = Ubar dV^T: one MFMA with k = the velocity component
     v4d dB = __builtin_amdgcn_mfma_f64_16x16x4f64(ub, dv, zero4, 0, 0, 0);
@@ -469,7 +474,7 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
     const double u = cj ? Um[0] : 0.0;
     const double zt = cj ? Vm[0] : 0.0;
     const double eu = row_chain(0.0, ej * u, N);
-    const double d0 = -eu / sigma;
+    const double d0 = -eu * rsig;
     const double zt_sum = row_chain(0.0, zt, N);
     if (comp) {
       const int64_t base = (int64_t)(g * n1) * ld + cell;
@@ -483,7 +488,7 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
       }
     }
     // direct dependence of the gas update on e, summed over components
-    const double ge_dir = groups_sum(cj ? (-d0 - u) * (Wsum / sigma) : 0.0);
+    const double ge_dir = groups_sum(cj ? (-d0 - u) * (Wsum * rsig) : 0.0);
     // column sums and diagonal of dL/dAt (D layout: rows 4v+g of column j)
     const double col = groups_sum(dY[0] + dY[1] + dY[2] + dY[3]);
     double dg = 0.0;
@@ -492,7 +497,7 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
       if (4 * v + g == j) dg = dY[v];
     dg = groups_sum(dg);
     if (g == 0) {
-      const double rg = A.rho_g[cell];
+      const double rrg = 1.0 / A.rho_g[cell];
       double ge = 0.0;
       if (j < N) {
         const double ga = -dg - ej * col;
@@ -500,10 +505,10 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
         const double glt = -aj * ga;
         if (A.g_logt) A.g_logt[j * ld + cell] = glt;
         if (A.g_t) A.g_t[j * ld + cell] = glt / A.t_stop[j * ld + cell];
-        if (A.g_rho_d) A.g_rho_d[j * ld + cell] = ge / rg;
+        if (A.g_rho_d) A.g_rho_d[j * ld + cell] = ge * rrg;
       }
       const double sum_ege = row_chain(0.0, ej * ge, N);
-      if (j == 0 && A.g_rho_g) A.g_rho_g[cell] = -sum_ege / rg;
+      if (j == 0 && A.g_rho_g) A.g_rho_g[cell] = -sum_ege * rrg;
     }
   }
 }
@@ -535,6 +540,44 @@ __global__ void __launch_bounds__(256) k_backward_wave(BackArgs A, int xcd_block
 // second 8 + i); rows and columns of species >= N are zero.  A wavefront
 // takes a quad of cells, set up once as in the forward kernel.
 
+// T_m(X) - I for a dense tile X by the Paterson-Stockmeyer scheme with Q
+// powers, all products on the matrix cores (XA: X as the A operand).
+template <int Q>
+__device__ __forceinline__ v4d mfma_poly(const v4d& X, const double (&XA)[4], int r,
+                                         double* stage, int g, int j) {
+  const v4d zero4 = {0.0, 0.0, 0.0, 0.0};
+  v4d P[Q + 1];
+  P[1] = X;
+#pragma unroll
+  for (int p = 2; p <= Q; ++p) {
+    double Bp[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Bp[t] = P[p - 1][t];
+    P[p] = mma16(XA, Bp, zero4);
+  }
+  double Bq[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) Bq[t] = P[Q][t];
+  auto bbar = [&](int k) {
+    v4d acc = zero4;
+#pragma unroll
+    for (int p = 1; p <= Q; ++p) {
+      const double cf = kInvFact[Q * k + p];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = fma(cf, P[p][v], acc[v]);
+    }
+    return acc;
+  };
+  v4d F = bbar(r - 1);
+  for (int k = r - 2; k >= 0; --k) {
+    double Af[4];
+    stage_tile(stage, g, j, F);
+    load_a_ops(stage, g, j, Af);
+    F = mma16(Af, Bq, bbar(k));
+  }
+  return F;
+}
+
 __device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, const int N,
                                                          int64_t c0, int lane, double* lds) {
   const int g = lane >> 4, j = lane & 15;
@@ -550,6 +593,7 @@ __device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, cons
 
   const QuadCell Q = quad_setup(A.rho_g, A.rho_d, A.t_stop, A.n_cells, ld, A.dt, A.k_max,
                                 A.option, N, c0, g, j, qa, qe, qp);
+  const double rsig_q = 1.0 / Q.sig;  // 1 / sigma of the row's cell
   const int diag_slot = j * kLdsStride + j;
 
   // velocity and weight data, lane (g = component, j): species jj
@@ -600,7 +644,7 @@ __device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, cons
     const int kp = __builtin_amdgcn_readlane(Q.kpack, 16 * c);
     const int kk = kp & 15, s = kp >> 4;
     const int q = kTabQ[kk], r = kTabR[kk];
-    const double sigma = readlane_f64(Q.sig, 16 * c);
+    const double rsig = readlane_f64(rsig_q, 16 * c);
 
     const int sj = 16 * c + quad_slot(jj);
     const double ej = qe[sj], aj = qa[sj];
@@ -616,7 +660,7 @@ __device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, cons
     // W_c (lane row g = component c), ubar, dv
     const double Wsum = row_chain(w0, cj && j < 8 ? wj : 0.0, 8);
     const double dv = cj ? vj - v0 : 0.0;
-    const double ub = cj ? wj - Wsum * ej / sigma : 0.0;
+    const double ub = cj ? wj - Wsum * ej * rsig : 0.0;
 
     // dB = 2^-s G at rows 0..7, columns 8..15: one MFMA over the components
     // (A[i][c] = ubar_c[i] from lanes j < 8, B[c][8 + k] = dv_c[k] from lanes
@@ -633,51 +677,18 @@ __device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, cons
       Xh[v] = diag_block ? val : ldexp(Xh[v], -s);
     }
 
-    // powers P_jj = Xh^jj on the matrix cores: Xh is the A operand for all
-    // of them (one LDS transposition), each power the B operand of the next
+    // powers Xh^p on the matrix cores: Xh is the A operand for all of them
+    // (one LDS transposition), each power the B operand of the next
     double XA[4];
     stage_tile(stage, g, j, Xh);
     load_a_ops(stage, g, j, XA);
-    v4d P[6];
-    P[1] = Xh;
-#pragma unroll
-    for (int p = 2; p <= 5; ++p) {
-      if (p <= q) {
-        double Bp[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) Bp[t] = P[p - 1][t];
-        P[p] = mma16(XA, Bp, zero4);
-      } else {
-        P[p] = zero4;
-      }
-    }
-    double Bq[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) Bq[t] = P[1][t];
-#pragma unroll
-    for (int p = 2; p <= 5; ++p)
-      if (p == q) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) Bq[t] = P[p][t];
-      }
-    auto bbar = [&](int k) {
-      v4d acc = zero4;
-#pragma unroll
-      for (int p = 1; p <= 5; ++p) {
-        if (p <= q) {
-          const double cf = kInvFact[q * k + p];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[v] = fma(cf, P[p][v], acc[v]);
-        }
-      }
-      return acc;
-    };
-    v4d F = bbar(r - 1);
-    for (int k = r - 2; k >= 0; --k) {
-      double Af[4];
-      stage_tile(stage, g, j, F);
-      load_a_ops(stage, g, j, Af);
-      F = mma16(Af, Bq, bbar(k));
+    v4d F;
+    switch (q) {  // uniform; one code path per power count
+      case 1: F = mfma_poly<1>(Xh, XA, r, stage, g, j); break;
+      case 2: F = mfma_poly<2>(Xh, XA, r, stage, g, j); break;
+      case 3: F = mfma_poly<3>(Xh, XA, r, stage, g, j); break;
+      case 4: F = mfma_poly<4>(Xh, XA, r, stage, g, j); break;
+      default: F = mfma_poly<5>(Xh, XA, r, stage, g, j); break;
     }
     // squarings of the block matrix, (Yh + 2 I) Yh
     v4d Y = F;
@@ -708,7 +719,7 @@ __device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, cons
     const double u = (cj && j < 8) ? Um[0] : 0.0;
     const double zt = (cj && j < 8) ? Vm[0] : 0.0;
     const double eu = row_chain(0.0, ej * u, 8);
-    const double d0 = -eu / sigma;
+    const double d0 = -eu * rsig;
     const double zt_sum = row_chain(0.0, zt, 8);
     if (comp && j < 8) {
       const int64_t base = (int64_t)(g * n1) * ld + cell;
@@ -722,7 +733,7 @@ __device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, cons
       }
     }
     // direct dependence of the gas update on e, summed over components
-    const double ge_dir = groups_sum(cj ? (-d0 - u) * (Wsum / sigma) : 0.0);
+    const double ge_dir = groups_sum(cj ? (-d0 - u) * (Wsum * rsig) : 0.0);
     // column sums and diagonal of dY (upper-right block, rows 4v+g, v < 2,
     // column 8 + k), moved to lane k of each row
     double col = (j < 8) ? 0.0 : Y[0] + Y[1];
@@ -733,7 +744,7 @@ __device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, cons
     col = row_ror64<8>(groups_sum(col));
     dg = row_ror64<8>(groups_sum(dg));
     if (g == 0) {
-      const double rg = A.rho_g[cell];
+      const double rrg = 1.0 / A.rho_g[cell];
       double ge = 0.0;
       if (j < N) {
         const double ga = -dg - ej * col;
@@ -741,10 +752,10 @@ __device__ __forceinline__ void wave_backward_block_quad(const BackArgs& A, cons
         const double glt = -aj * ga;
         if (A.g_logt) A.g_logt[j * ld + cell] = glt;
         if (A.g_t) A.g_t[j * ld + cell] = glt / A.t_stop[j * ld + cell];
-        if (A.g_rho_d) A.g_rho_d[j * ld + cell] = ge / rg;
+        if (A.g_rho_d) A.g_rho_d[j * ld + cell] = ge * rrg;
       }
       const double sum_ege = row_chain(0.0, ej * ge, N);
-      if (j == 0 && A.g_rho_g) A.g_rho_g[cell] = -sum_ege / rg;
+      if (j == 0 && A.g_rho_g) A.g_rho_g[cell] = -sum_ege * rrg;
     }
   }
 }

@@ -123,7 +123,7 @@ static int launch_backward_lane(const BackArgs& A, hipStream_t st) {
 
 template <int N>
 static int launch_backward_wave(const BackArgs& A, hipStream_t st) {
-  const Grid gr = grid_for((A.n_cells + 3) / 4);
+  const Grid gr = grid_for((A.n_cells + 15) / 16);  // a quad of cells per wavefront
   hipLaunchKernelGGL(k_backward_wave<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
   return hip_status(hipGetLastError());
 }

@@ -51,23 +51,31 @@ __device__ __forceinline__ void lane_taylor(double (&F)[N][N], const double (&b)
   }
 }
 
-// One Y-form squaring Z <- 2 Z + Z Z (the paper's X <- X X with X = I + Z).
+// One Y-form squaring W <- 2 Z + Z Z (the paper's X <- X X with X = I + Z),
+// written as Z (Z + 2 I): the right factor's diagonal gets 2, so no separate
+// 2 Z term.  The extra rounding of 2 + Z_ll is of the size of the sum's own.
 template <int N>
-__device__ __forceinline__ void lane_square(double (&Z)[N][N]) {
-  double T[N][N];
+__device__ __forceinline__ void lane_square_to(double (&W)[N][N], const double (&Z)[N][N]) {
+  double d[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) d[l] = Z[l][l] + 2.0;
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      double acc = 2.0 * Z[i][k];
+      double acc = Z[i][0] * (k == 0 ? d[0] : Z[0][k]);
 #pragma unroll
-      for (int l = 0; l < N; ++l) acc = fma(Z[i][l], Z[l][k], acc);
-      T[i][k] = acc;
+      for (int l = 1; l < N; ++l) acc = fma(Z[i][l], l == k ? d[l] : Z[l][k], acc);
+      W[i][k] = acc;
     }
+}
+
+template <int N>
+__device__ __forceinline__ void lane_copy(double (&W)[N][N], const double (&Z)[N][N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int k = 0; k < N; ++k) Z[i][k] = T[i][k];
+    for (int k = 0; k < N; ++k) W[i][k] = Z[i][k];
 }
 
 __device__ __forceinline__ int wave_max_int(int x) {
@@ -142,9 +150,21 @@ __device__ __forceinline__ void lane_expm(double (&Z)[N][N], const LaneCell<N>& 
   }
   const int m_max = wave_max_int(C.kms.m);
   lane_taylor<N>(Z, b, pb, C.kms.m, m_max);
-  const int s_max = wave_max_int(C.kms.s);
-  for (int it = 0; it < s_max; ++it) {
-    if (it < C.kms.s) lane_square<N>(Z);
+  // squarings to the wavefront's largest s, each lane under its own s; two
+  // per trip between Z and T so that no copy is needed on the common path
+  const int s = C.kms.s;
+  const int s_max = wave_max_int(s);
+  double T[N][N];
+  int it = 0;
+  for (; it + 2 <= s_max; it += 2) {
+    if (it < s) lane_square_to<N>(T, Z);
+    else lane_copy<N>(T, Z);
+    if (it + 1 < s) lane_square_to<N>(Z, T);
+    else lane_copy<N>(Z, T);
+  }
+  if (it < s) {
+    lane_square_to<N>(T, Z);
+    lane_copy<N>(Z, T);
   }
 }
 
