@@ -17,6 +17,7 @@
 #include "lane.hpp"
 #include "wave.hpp"
 #include "adjoint.hpp"
+#include "pair.hpp"
 #include "batched.hpp"
 
 namespace dragexp {
@@ -121,6 +122,14 @@ static int launch_backward_lane(const BackArgs& A, hipStream_t st) {
   return hip_status(hipGetLastError());
 }
 
+// two lanes per cell (pair.hpp), 128 cells per workgroup
+template <int N>
+static int launch_backward_pair(const BackArgs& A, hipStream_t st) {
+  const Grid gr = grid_for((A.n_cells + 127) / 128);
+  hipLaunchKernelGGL(k_backward_pair<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
 template <int N>
 static int launch_backward_wave(const BackArgs& A, hipStream_t st) {
   const Grid gr = grid_for((A.n_cells + 15) / 16);  // a quad of cells per wavefront
@@ -151,7 +160,7 @@ static BwdFn lane_bwd(int N) {
   static const BwdFn tab[kLaneMaxN] = {
       launch_backward_lane<1>, launch_backward_lane<2>, launch_backward_lane<3>,
       launch_backward_lane<4>, launch_backward_lane<5>, launch_backward_lane<6>,
-      launch_backward_lane<7>, launch_backward_lane<8>};
+      launch_backward_lane<7>, launch_backward_pair<8>};
   return tab[N - 1];
 }
 
@@ -183,14 +192,14 @@ static int g_default_map[16] = {
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
 static int g_map_override[16] = {0};
 
-// Default mapping of the adjoint.  The lane kernel keeps three N x N
-// matrices per lane and spills at N = 8; there the MFMA block form (Y and dY
-// on one 16 x 16 tile, one product per squaring) is faster (measured on
-// MI355X, 2^18 stiff cells: lane 1.68 ms, block 1.21 ms), while for N <= 7
-// the lane kernel wins.
+// Default mapping of the adjoint.  The lane mapping keeps Y, dY and a
+// product buffer per cell in registers: one lane per cell up to N = 7, two
+// lanes per cell at N = 8, where one lane spills (pair.hpp).  Measured on
+// MI355X (2^18 stiff cells): N = 8 one lane 1.64 ms, two lanes 0.77 ms, MFMA
+// block form 1.08 ms; N = 7 one lane 0.54 ms, MFMA 1.07 ms.
 static int g_default_map_bwd[16] = {
     DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
-    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_WAVE,
+    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
 

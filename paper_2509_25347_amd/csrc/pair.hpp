@@ -1,0 +1,348 @@
+// pair.hpp -- the fused forward + adjoint with two lanes per cell (used at
+// N = 8; valid for any N <= 8).
+//
+// The one-lane adjoint keeps Y, dY and a product buffer (3 N^2 doubles) in
+// one lane: at N = 8 that exceeds the register file and spills.  Here the two
+// lanes 2p, 2p+1 of a pair share cell p: lane h holds rows h H .. h H + H - 1
+// (H = ceil(N / 2)) of Y and dY, so each lane keeps 2 H^2 + H 2H doubles
+// instead of 3 N^2.
+//
+// Column order.  Every lane stores its rows with the columns in a
+// lane-relative order: first the H columns of its own half, then the H of
+// the other half (relative column kappa <-> global column h H + kappa for
+// kappa < H, (1 - h) H + kappa - H otherwise).  Then all register indices are
+// compile-time constants: the diagonal element of own row r is column r,
+// the partner's row r' is global row (1 - h) H + r' = relative column H + r',
+// and the partner's copy of a register, fetched with one DPP quad_perm swap
+// per dword, maps its relative column kappa_p to mine by a half rotation
+// (kappa = (kappa_p + H) mod 2H).
+//
+// The recurrences are those of the one-lane kernel (adjoint.hpp): Horner in
+// B = M^T with the Frechet derivative in the direction dB = 2^-s G, then the
+// squarings dY <- dY (Y + 2I) + Y dY, Y <- Y (Y + 2I).  The products of the
+// Horner stage are row-local (no exchange); each squaring fetches the
+// partner's rows of Y and dY once (and Y again for the second product).
+// dB = 2^-s sum_c ubar_c dv_c^T is used in its rank-D form: h dB = 2^-s
+// sum_c (h . ubar_c) dv_c^T, with ubar and dv kept in LDS.
+#pragma once
+
+#include "common.hpp"
+#include "lane.hpp"
+
+namespace dragexp {
+
+// The other lane's value of x in the pair (DPP quad_perm [1, 0, 3, 2]).
+__device__ __forceinline__ double pair_swap(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0xB1, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// x(lane 0 of the pair) + x(lane 1): the same bits in both lanes.
+__device__ __forceinline__ double pair_sum(double x, int h) {
+  const double y = pair_swap(x);
+  return h == 0 ? x + y : y + x;
+}
+
+// kMinWaves: waves per SIMD the register allocation must allow (2 forces
+// N = 7, 8 into 256 registers at the price of a few spills in the squaring
+// loop; 1 lets them use accumulation registers instead).
+template <int N, int kMinWaves = 2>
+__global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, int xcd_blocks) {
+  constexpr int H = (N + 1) / 2;  // rows per lane
+  constexpr int W2 = 2 * H;       // padded width
+  constexpr int kCells = 128;     // cells per workgroup (two lanes each)
+  // per cell, global column order, zero padded: ubar[3][W2], dv[3][W2], a[W2], e[W2]
+  constexpr int kPer = 8 * W2;
+  __shared__ double sm[kCells * kPer];
+
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int pl = threadIdx.x >> 1;  // pair within the workgroup
+  const int h = threadIdx.x & 1;    // half
+  const int64_t c = logical * kCells + pl;
+  const bool active = c < A.n_cells;
+  const int64_t cc = active ? c : 0;  // an inactive pair computes on cell 0, stores nothing
+  const int64_t ld = A.ld;
+  const int n1 = N + 1;
+  const int D = A.n_dim;
+  double* my = sm + pl * kPer;
+
+  // relative column kappa of this lane <-> global column
+  auto gcol = [&](int kappa) { return kappa < H ? h * H + kappa : (1 - h) * H + kappa - H; };
+
+  LaneCell<N> C;
+  lane_setup<N>(C, A.rho_g, A.rho_d, A.t_stop, ld, cc, A.dt, A.k_max, A.option);
+  bool fin = true;
+  for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int j = 0; j <= N; ++j) {
+      const int64_t idx = (int64_t)(d * n1 + j) * ld + cc;
+      fin = fin && isfinite(A.v_in[idx]) && isfinite(A.w[idx]);
+    }
+  }
+  if (!fin && !C.bad) C.bad = kBadVelocity;
+  if (C.bad) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) C.a[i] = C.e[i] = C.p[i] = 0.0;
+    C.sigma = 1.0;
+    C.kms = select_kms(0.0, A.k_max, A.option);
+  }
+  const int s = C.kms.s, m = C.kms.m;
+
+  // scaled coefficients in this lane's relative order
+  double nb[W2], npb[W2];
+#pragma unroll
+  for (int kap = 0; kap < W2; ++kap) {
+    const int g = gcol(kap);
+    double a = 0.0, p = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {  // select by value: no private-array indexing
+      a = (g == k) ? C.a[k] : a;
+      p = (g == k) ? C.p[k] : p;
+    }
+    nb[kap] = -ldexp(a, -s);
+    npb[kap] = -ldexp(p, -s);
+  }
+
+  // ubar and dv of every component to LDS (lane 0 of the pair writes)
+  if (h == 0) {
+    for (int d = 0; d < 3; ++d) {
+      double v[N + 1], w[N + 1];
+      double W = 0.0;
+#pragma unroll
+      for (int j = 0; j <= N; ++j) {
+        const int64_t idx = (int64_t)(d * n1 + j) * ld + cc;
+        v[j] = (d < D && !C.bad) ? A.v_in[idx] : 0.0;
+        w[j] = (d < D && !C.bad) ? A.w[idx] : 0.0;
+        W += w[j];
+      }
+#pragma unroll
+      for (int k = 0; k < W2; ++k) {
+        my[d * W2 + k] = k < N ? w[k + 1] - W * C.e[k < N ? k : 0] / C.sigma : 0.0;
+        my[(3 + d) * W2 + k] = k < N ? v[k + 1] - v[0] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < W2; ++k) {
+      my[6 * W2 + k] = k < N ? C.a[k < N ? k : 0] : 0.0;
+      my[7 * W2 + k] = k < N ? C.e[k < N ? k : 0] : 0.0;
+    }
+  }
+  const double sigma = C.sigma;
+  const unsigned bad = C.bad;
+  __syncthreads();
+
+  // Horner in B = M^T with its derivative:
+  //   Y  <- (Y + c I) B,  dY <- dY B + (Y + c I) dB,  (X B)_ik = -X_ik b_k - (X pb)_i
+  double Y[H][W2], dY[H][W2];
+#pragma unroll
+  for (int r = 0; r < H; ++r)
+#pragma unroll
+    for (int k = 0; k < W2; ++k) Y[r][k] = dY[r][k] = 0.0;
+  const int m_max = wave_max_int(m);
+  for (int it = m_max; it >= 1; --it) {
+    const double cf = (it <= m) ? kInvFact[it] : 0.0;
+    double hp[H], fp[H];
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      Y[r][r] += cf;  // own row r is global row h H + r = relative column r
+      hp[r] = 0.0;
+      fp[r] = 0.0;
+#pragma unroll
+      for (int k = 0; k < W2; ++k) {
+        hp[r] = fma(Y[r][k], -npb[k], hp[r]);
+        fp[r] = fma(dY[r][k], -npb[k], fp[r]);
+      }
+#pragma unroll
+      for (int k = 0; k < W2; ++k) dY[r][k] = fma(dY[r][k], nb[k], -fp[r]);
+    }
+    // + (Y + cI) dB = 2^-s sum_d ((Y + cI) ubar_d) dv_d^T
+    for (int d = 0; d < D; ++d) {
+      double ub[W2], dv[W2];
+#pragma unroll
+      for (int k = 0; k < W2; ++k) {
+        const int g = gcol(k);
+        ub[k] = my[d * W2 + g];
+        dv[k] = my[(3 + d) * W2 + g];
+      }
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < W2; ++k) t = fma(Y[r][k], ub[k], t);
+        t = ldexp(t, -s);
+#pragma unroll
+        for (int k = 0; k < W2; ++k) dY[r][k] = fma(t, dv[k], dY[r][k]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < H; ++r)
+#pragma unroll
+      for (int k = 0; k < W2; ++k) Y[r][k] = fma(Y[r][k], nb[k], -hp[r]);
+  }
+
+  // squarings with the Frechet recurrence: dY <- dY (Y + 2I) + Y dY, then
+  // Y <- Y (Y + 2I); the partner's rows come by DPP, columns half-rotated
+  const int s_max = wave_max_int(s);
+  for (int it = 0; it < s_max; ++it) {
+    if (it < s) {
+      double T[H][W2];
+#pragma unroll
+      for (int r = 0; r < H; ++r)
+#pragma unroll
+        for (int k = 0; k < W2; ++k) T[r][k] = 0.0;
+      // own rows r2 (relative column r2 of a row of mine)
+#pragma unroll
+      for (int r2 = 0; r2 < H; ++r2) {
+#pragma unroll
+        for (int r = 0; r < H; ++r)
+#pragma unroll
+          for (int k = 0; k < W2; ++k) {
+            const double wv = Y[r2][k] + (k == r2 ? 2.0 : 0.0);
+            T[r][k] = fma(dY[r][r2], wv, fma(Y[r][r2], dY[r2][k], T[r][k]));
+          }
+      }
+      // partner rows r2 (relative column H + r2 of a row of mine), fetched
+      // one element at a time to keep the live set small
+#pragma unroll
+      for (int r2 = 0; r2 < H; ++r2)
+#pragma unroll
+        for (int k = 0; k < W2; ++k) {
+          const double py = pair_swap(Y[r2][(k + H) % W2]) + (k == H + r2 ? 2.0 : 0.0);
+          const double pdy = pair_swap(dY[r2][(k + H) % W2]);
+#pragma unroll
+          for (int r = 0; r < H; ++r)
+            T[r][k] = fma(dY[r][H + r2], py, fma(Y[r][H + r2], pdy, T[r][k]));
+        }
+#pragma unroll
+      for (int r = 0; r < H; ++r)
+#pragma unroll
+        for (int k = 0; k < W2; ++k) dY[r][k] = T[r][k];
+      // Y <- Y (Y + 2I)
+#pragma unroll
+      for (int r = 0; r < H; ++r)
+#pragma unroll
+        for (int k = 0; k < W2; ++k) T[r][k] = 0.0;
+#pragma unroll
+      for (int r2 = 0; r2 < H; ++r2) {
+#pragma unroll
+        for (int r = 0; r < H; ++r)
+#pragma unroll
+          for (int k = 0; k < W2; ++k)
+            T[r][k] = fma(Y[r][r2], Y[r2][k] + (k == r2 ? 2.0 : 0.0), T[r][k]);
+      }
+#pragma unroll
+      for (int r2 = 0; r2 < H; ++r2)
+#pragma unroll
+        for (int k = 0; k < W2; ++k) {
+          const double py = pair_swap(Y[r2][(k + H) % W2]) + (k == H + r2 ? 2.0 : 0.0);
+#pragma unroll
+          for (int r = 0; r < H; ++r) T[r][k] = fma(Y[r][H + r2], py, T[r][k]);
+        }
+#pragma unroll
+      for (int r = 0; r < H; ++r)
+#pragma unroll
+        for (int k = 0; k < W2; ++k) Y[r][k] = T[r][k];
+    }
+  }
+
+  // outputs: Y = Z^T, dY = dL/dAt (rows of this lane).  Own species are the
+  // global indices h H + r, r < H (own rows = own-half relative columns).
+  const double qnan = __builtin_nan("");
+  const double rg = A.rho_g[cc];
+  const double rsig = 1.0 / sigma;
+  double ge_dir[H];
+#pragma unroll
+  for (int r = 0; r < H; ++r) ge_dir[r] = 0.0;
+  for (int d = 0; d < D; ++d) {
+    double ub[W2], dv[W2];
+#pragma unroll
+    for (int k = 0; k < W2; ++k) {
+      const int g = gcol(k);
+      ub[k] = my[d * W2 + g];
+      dv[k] = my[(3 + d) * W2 + g];
+    }
+    // u = Z dv: column sums of Y weighted by dv over own rows, plus the partner's
+    double up[W2];
+#pragma unroll
+    for (int k = 0; k < W2; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < H; ++r) acc = fma(Y[r][k], dv[r], acc);  // dv of own row r
+      up[k] = acc;
+    }
+    double u[W2];
+#pragma unroll
+    for (int k = 0; k < W2; ++k) u[k] = up[k] + pair_swap(up[(k + H) % W2]);
+    double eu_own = 0.0, zt[H], zt_own = 0.0;
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      const double e_r = my[7 * W2 + h * H + r];
+      eu_own = fma(e_r, u[r], eu_own);
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < W2; ++k) acc = fma(Y[r][k], ub[k], acc);  // (Z^T ubar)_(own row r)
+      zt[r] = acc;
+      zt_own += acc;
+    }
+    const double eu = pair_sum(eu_own, h);
+    const double d0 = -eu * rsig;
+    const double zt_sum = pair_sum(zt_own, h);
+    double W = 0.0;
+    const int64_t base = (int64_t)(d * n1) * ld + c;
+#pragma unroll
+    for (int j = 0; j <= N; ++j) W += A.w[(int64_t)(d * n1 + j) * ld + cc];
+#pragma unroll
+    for (int r = 0; r < H; ++r) ge_dir[r] = fma(-d0 - u[r], W * rsig, ge_dir[r]);
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        const int k = h * H + r;
+        if (k < N) {
+          const int64_t idx = base + (int64_t)(1 + k) * ld;
+          if (A.v_out) A.v_out[idx] = bad ? qnan : A.v_in[idx] + (d0 + u[r]);
+          if (A.g_v) A.g_v[idx] = bad ? qnan : A.w[idx] + zt[r];
+        }
+      }
+      if (h == 0) {
+        if (A.v_out) A.v_out[base] = bad ? qnan : A.v_in[base] + d0;
+        if (A.g_v) A.g_v[base] = bad ? qnan : A.w[base] - zt_sum;
+      }
+    }
+  }
+  // column sums and diagonal of dL/dAt for the own species
+  double colp[W2];
+#pragma unroll
+  for (int k = 0; k < W2; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < H; ++r) acc += dY[r][k];
+    colp[k] = acc;
+  }
+  double sum_ege = 0.0;
+#pragma unroll
+  for (int r = 0; r < H; ++r) {
+    const int k = h * H + r;
+    const double col = colp[r] + pair_swap(colp[(r + H) % W2]);
+    const double e_k = my[7 * W2 + h * H + r];
+    const double a_k = my[6 * W2 + h * H + r];
+    const double ga = -dY[r][r] - e_k * col;
+    const double ge = -a_k * col + ge_dir[r];
+    const double glt = -a_k * ga;
+    sum_ege = fma(e_k, ge, sum_ege);
+    if (active && k < N) {
+      if (A.g_logt) A.g_logt[k * ld + c] = bad ? qnan : glt;
+      if (A.g_t) A.g_t[k * ld + c] = bad ? qnan : glt / A.t_stop[k * ld + c];
+      if (A.g_rho_d) A.g_rho_d[k * ld + c] = bad ? qnan : ge / rg;
+    }
+  }
+  const double sum_all = pair_sum(sum_ege, h);
+  if (active && h == 0) {
+    if (A.g_rho_g) A.g_rho_g[c] = bad ? qnan : -sum_all / rg;
+    if (bad) atomicOr(&g_status_word, bad);
+  }
+}
+
+}  // namespace dragexp
