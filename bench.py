@@ -128,6 +128,9 @@ def main():
                     help="skip the fused-adjoint and batched comparisons against the plain forward")
     ap.add_argument("--extra", action="store_true",
                     help="also time the other workloads, the fused adjoint and the batched launch")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the fused forward + adjoint (drag_expm_apply_backward) on the "
+                         "workload instead of the forward (for profiling the adjoint kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times), the "
                          "reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -154,6 +157,9 @@ def main():
         return
 
     name = args.workload
+    if args.adjoint:
+        print(json.dumps(adjoint_only(torch, ops, _lib, workloads, dev, name, args)), flush=True)
+        return
     d = workloads.make(name, args.cells)
     C = d["rho_g"].shape[0]
     N = d["rho_d"].shape[0]
@@ -244,6 +250,20 @@ def _time(torch, fn, steps, warmup):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def adjoint_only(torch, ops, _lib, workloads, dev, name, args):
+    """The fused forward + adjoint on one workload (loss weights w ~ N(0, 1))."""
+    d = workloads.make(name, args.cells, with_weights=True)
+    T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v", "w")}
+    N = d["rho_d"].shape[0]
+    C = d["rho_g"].shape[0]
+    ms = _time(torch, lambda: ops.expm_apply_backward(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                      T["w"], d["dt"]), args.steps, args.warmup)
+    return {"metric": "FP64 fused forward + adjoint cell-updates/s", "value": C / (ms * 1e-3),
+            "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": name, "n_cells": C, "n_species": N}}
 
 
 def adjoint_measurement(torch, ops, workloads, dev):

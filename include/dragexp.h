@@ -25,10 +25,13 @@
  * share one matrix K.
  *
  * Ownership and synchronisation: every array pointer is a device pointer
- * owned by the caller.  Calls only enqueue work on `stream` (a hipStream_t;
- * NULL is the null stream); they never allocate device memory, never
- * synchronise, and return before the work is done -- except
- * drag_get_status, which synchronises `stream`.
+ * owned by the caller.  drag_build, drag_expm_apply, drag_expm_apply_backward
+ * and drag_clear_status only enqueue work on `stream` (a hipStream_t; NULL is
+ * the null stream): they never allocate device memory, never synchronise, and
+ * return before the work is done.  drag_get_status and drag_plan_autotune
+ * synchronise `stream`; the batched plan calls allocate and free the plan's
+ * own device tables and graph (drag_plan_batched, drag_plan_destroy, and a
+ * re-capture inside drag_expm_apply_batched when the pointers change).
  *
  * Errors: a negative return value is an argument error found on the host
  * before anything was enqueued.  Invalid per-cell data (rho_g not finite or
@@ -176,8 +179,9 @@ int drag_expm_apply_batched(drag_plan *plan, const double *fields,
 /* Time every launch configuration of the plan on the caller's data (each
  * run computes the full, valid result into v_out, then synchronises
  * `stream`), keep the fastest, and report its lane-mapping bound: blocks
- * with N_b <= *lane_max_out run one cell per lane, the others one cell per
- * wavefront on FP64 MFMA.  The next drag_expm_apply_batched re-captures. */
+ * with N_b <= *lane_max_out run one cell per lane, the others on the FP64
+ * MFMA path (a quad of cells per wavefront) in the form that timed fastest
+ * (drag_plan_config).  The next drag_expm_apply_batched re-captures. */
 int drag_plan_autotune(drag_plan *plan, const double *fields,
                        const double *v_in, double *v_out,
                        drag_stream_t stream, int32_t *lane_max_out);
@@ -212,9 +216,16 @@ int drag_select(double norm, int32_t k_max, int32_t option, int32_t *k,
                 int32_t *m, int32_t *s);
 
 /* ---- launch tuning ------------------------------------------------------------ */
-/* The per-N mapping used by drag_expm_apply and the batched plan:
- * DRAG_MAP_LANE (one cell per lane, VALU) or DRAG_MAP_WAVE (one cell per
- * 64-lane wavefront, FP64 MFMA).  DRAG_MAP_AUTO restores the tuned default. */
+/* The per-N mapping used by drag_expm_apply, drag_expm_apply_backward and
+ * the batched plan (for species count n_species, host-side, per process):
+ *   DRAG_MAP_LANE  vector ALU, one cell per lane (N <= 8 only; the adjoint
+ *                  at N = 8 runs one cell per pair of lanes);
+ *   DRAG_MAP_WAVE  FP64 MFMA: four cells per 64-lane wavefront, one
+ *                  exponential at a time on 16 x 16 tiles (the adjoint for
+ *                  N <= 8 on one tile holding the 2N x 2N block form);
+ *   DRAG_MAP_AUTO  the measured default (lane for N <= 8, MFMA above).
+ * DRAG_ERR_OPTION for an unknown mapping or LANE with N > 8.
+ * drag_get_mapping reports the forward's mapping. */
 #define DRAG_MAP_AUTO 0
 #define DRAG_MAP_LANE 1
 #define DRAG_MAP_WAVE 2

@@ -53,8 +53,9 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
   constexpr int H = (N + 1) / 2;  // rows per lane
   constexpr int W2 = 2 * H;       // padded width
   constexpr int kCells = 128;     // cells per workgroup (two lanes each)
-  // per cell, global column order, zero padded: ubar[3][W2], dv[3][W2], a[W2], e[W2]
-  constexpr int kPer = 8 * W2;
+  // per cell, global column order, zero padded: ubar[3][W2], dv[3][W2], a[W2], e[W2];
+  // the odd stride spreads the pairs of a wavefront over the LDS banks
+  constexpr int kPer = 8 * W2 + 1;
   __shared__ double sm[kCells * kPer];
 
   const int bid = blockIdx.x;

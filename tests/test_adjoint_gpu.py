@@ -118,13 +118,36 @@ def test_fused_forward_matches_forward(ops, dev):
         assert e.max() <= 1e-13, (name, e.max())
 
 
-def test_backward_vs_finite_differences(ops, dev):
+FD_CASES = {
+    # name: (cells, N for the mapping override or None, mapping)
+    "n8_adjoint_default": (lambda: W.make("n8_adjoint_3d", 6), None, None),
+    "n3_lane": (lambda: W.make_jittered(3, 5), 3, 1),
+    "n8_mfma_block": (lambda: W.make("n8_adjoint_3d", 6), 8, 2),
+    "n12_mfma": (lambda: W.make_stiff(12, 5), 12, 2),
+}
+
+
+@pytest.mark.parametrize("case", sorted(FD_CASES))
+def test_backward_vs_finite_differences(ops, dev, case):
     """Central differences of the GPU forward with h = 1e-6 in each
     parameter's natural scale: additive in log t_i and v, steps of h rho_g in
     rho_i (the scale of e_i = rho_i / rho_g; a step relative to a small rho_i
     would divide the forward's rounding noise by a tiny number) and relative
-    in rho_g.  Agreement to 1e-7 of the group scale."""
-    d = _weights(W.make("n8_adjoint_3d", 6), seed=3)
+    in rho_g.  Agreement to 1e-7 of the group scale.  One case per adjoint
+    kernel: one lane per cell, two lanes per cell (the N = 8 default), the
+    MFMA block form and the MFMA kernel for N >= 9."""
+    from paper_2509_25347_amd import _lib
+    make, n_map, mapping = FD_CASES[case]
+    if n_map is not None:
+        _lib.set_mapping(n_map, mapping)
+    try:
+        _fd_check(ops, dev, _weights(make(), seed=3))
+    finally:
+        if n_map is not None:
+            _lib.set_mapping(n_map, _lib.MAP_AUTO)
+
+
+def _fd_check(ops, dev, d):
     T = _to(d, dev)
     _, g_v, g_logt, g_rho, g_rho_g = ops.expm_apply_backward(
         T["rho_g"], T["rho_d"], T["t_stop"], T["v"], T["w"], d["dt"])
