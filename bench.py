@@ -47,14 +47,23 @@ def algorithmic_flops(k, m, s, N, D):
             + 2.0 * m * n ** 2 + 2.0 * D * n ** 2)
 
 
+# Paterson-Stockmeyer split (q, r) of the MFMA forward per k (structured
+# powers are cheap there; see csrc/wave.hpp kPsQ / kPsR)
+PS_Q = {1: 2, 2: 4, 3: 3, 4: 5, 5: 4, 6: 4, 7: 5, 8: 5, 9: 5}
+PS_R = {1: 1, 2: 1, 3: 2, 4: 2, 5: 3, 6: 4, 7: 4, 8: 5, 9: 6}
+
+
 def executed_flops(k, m, s, N, D, mapping):
-    """FP64 flops the library executes per cell: the same products on the
-    N x N relative-velocity block (16 x 16 MFMA tiles for the wave kernel)."""
-    q = np.vectorize(TABLE_Q.get)(k)
-    r = np.vectorize(TABLE_R.get)(k)
+    """FP64 flops the library executes per cell.  MFMA kernel: (r-1) Horner
+    products, s squarings and the apply on 16 x 16 tiles (2 * 16^3 each),
+    (q-1) structured powers (4 * 16^2) and the B-bar sums (2 * 16^2 per
+    coefficient, q r of them).  Lane kernel: Horner in the structured matrix
+    (4 N^2 per degree), s squarings (2 N^3) and the apply (2 D N^2)."""
     if mapping == "wave":
         t = 16
-        return (r - 1 + s + q - 1 + 1) * 2.0 * t ** 3 + 2.0 * m * t * t
+        q = np.vectorize(PS_Q.get)(k)
+        r = np.vectorize(PS_R.get)(k)
+        return (r - 1 + s + 1) * 2.0 * t ** 3 + (q - 1) * 4.0 * t * t + 2.0 * q * r * t * t
     return (s * 2.0 * N ** 3 + m * 4.0 * N * N + 2.0 * D * N * N)
 
 

@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(256) k_batched_wave(BatchArgs B) {
 // compiled for it like the plain per-N kernels.  The autotuner picks among
 // the persistent grid, one run-time-N grid and the per-N grids.
 template <int NC>
-__global__ void __launch_bounds__(256) k_batched_wave_grid(BatchArgs B, int groups_per_block,
+__global__ void __launch_bounds__(256, 5) k_batched_wave_grid(BatchArgs B, int groups_per_block,
                                                            int xcd_blocks) {
   __shared__ double lds[4 * kQuadDoubles];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -103,11 +103,15 @@ __global__ void __launch_bounds__(256) k_batched_wave_grid(BatchArgs B, int grou
   // contiguous run of workgroups, hence whole blocks
   const int wg = (blockIdx.x & 7) * xcd_blocks + (blockIdx.x >> 3);
   const int item = __builtin_amdgcn_readfirstlane(wg / groups_per_block);
-  const int c0 = __builtin_amdgcn_readfirstlane((wg % groups_per_block) * 16 + 4 * w);
-  if (item >= B.n_items || c0 >= B.block_cells) return;  // uniform over the wavefront
+  const int g0 = __builtin_amdgcn_readfirstlane((wg % groups_per_block) * 16);
+  if (item >= B.n_items || g0 >= B.block_cells) return;  // uniform over the workgroup
   const BatchItem it = B.items[item];  // one whole block
   const CellArgs A = block_args(B, it);
-  wave_forward_quad(A, NC > 0 ? NC : it.n, c0, lane, lds + w * kQuadDoubles);
+  const int n = NC > 0 ? NC : it.n;
+  const int c0 = g0 + 4 * w;
+  if (c0 < B.block_cells) wave_forward_quad(A, n, c0, lane, lds + w * kQuadDoubles, false);
+  __syncthreads();
+  group_store(A, n, g0, lds);
 }
 
 // One 64-cell lane item per wavefront, all items of one species count N.

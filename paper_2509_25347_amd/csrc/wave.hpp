@@ -145,7 +145,8 @@ __device__ __forceinline__ double row_chain(double acc, double x, const int N) {
 // Per-wavefront LDS: the A-operand staging tile and the quad's coefficients.
 // Species j of quad cell c sits at 16 c + (4 (j & 3) + (j >> 2)), so the four
 // species 4 v + g (v = 0..3) that lane 16 g + j needs are contiguous.
-constexpr int kQuadDoubles = kStageDoubles + 3 * 64;
+constexpr int kQuadVel = 3 * 17 * 4;  // velocities of the quad: [D (N+1)][4 cells]
+constexpr int kQuadDoubles = kStageDoubles + 3 * 64 + kQuadVel;
 
 __device__ __forceinline__ int quad_slot(int j) { return 4 * (j & 3) + (j >> 2); }
 
@@ -167,13 +168,23 @@ __device__ __forceinline__ v4d mul_M(const v4d& X, const QuadRows& R, const doub
   return Y;
 }
 
+// Split m <= q r of the Paterson-Stockmeyer evaluation used by the MFMA
+// forward.  Table B.1 chooses (q, r) to minimise dense products; here the
+// powers are structured products on the vector ALU (about 72 cycles per cell
+// each, against 256 for a 16 x 16 MFMA product), so the cheapest split of the
+// same degree shifts toward more powers: minimise 72 (q - 1) + 256 (r - 1) +
+// 16 q r (the B-bar sums) over q <= 5, r = ceil(m / q).  Coefficients of
+// degree above m are zero, so every split evaluates the same T_m.
+constexpr int kPsQ[10] = {0, 2, 4, 3, 5, 4, 4, 5, 5, 5};
+constexpr int kPsR[10] = {0, 1, 1, 2, 2, 3, 4, 4, 5, 6};
+
 // T_m(M) - I by the Paterson-Stockmeyer scheme with Q powers (Sect. 2.3):
 // P_jj = M^jj in the structured form, Bbar_k = sum_{jj=1}^{Q} b_{Qk+jj} P_jj,
 // then Horner F = Bbar_{r-1}; F = Bbar_k + F P_Q, k = r-2..0 on the matrix
 // cores (P_Q is the B operand straight from registers).
 template <int Q>
 __device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const double (&rm)[4],
-                                         int r, double* stage, int g, int j) {
+                                         int m, int r, double* stage, int g, int j) {
   v4d P[Q + 1];
   P[1] = M;
 #pragma unroll
@@ -185,7 +196,7 @@ __device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const 
     v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int jj = 1; jj <= Q; ++jj) {
-      const double cf = kInvFact[Q * k + jj];
+      const double cf = (Q * k + jj <= m) ? kInvFact[Q * k + jj] : 0.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[v] = fma(cf, P[jj][v], acc[v]);
     }
@@ -274,8 +285,10 @@ __device__ __forceinline__ QuadCell quad_setup(const double* rho_g, const double
   return Q;
 }
 
+// With store = false the outputs stay in the quad's LDS block (vs) for the
+// workgroup to store (group_store).
 __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N, int64_t c0,
-                                                  int lane, double* lds) {
+                                                  int lane, double* lds, bool store = true) {
   const int g = lane >> 4, j = lane & 15;
   const int64_t ld = A.ld;
   const int n1 = N + 1;
@@ -287,9 +300,17 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
 
   const QuadCell Q = quad_setup(A.rho_g, A.rho_d, A.t_stop, A.n_cells, ld, A.dt, A.k_max,
                                 A.option, N, c0, g, j, qa, qe, qp);
-  const unsigned bad = Q.bad;
-  const int kpack = Q.kpack;
+  // the four cells' bad bits, (k*, s*) and 1 / sigma as scalars
   const double rsig = 1.0 / Q.sig;
+  unsigned bad_s[4];
+  int kp_s[4];
+  double rsig_s[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    bad_s[r] = (unsigned)__builtin_amdgcn_readlane((int)Q.bad, 16 * r);
+    kp_s[r] = __builtin_amdgcn_readlane(Q.kpack, 16 * r);
+    rsig_s[r] = readlane_f64(rsig, 16 * r);
+  }
 
   // lane constants of the tile layout
   double rm[4];  // 1 for rows < N
@@ -297,46 +318,53 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
   for (int v = 0; v < 4; ++v) rm[v] = (4 * v + g < N) ? 1.0 : 0.0;
   const int diag_slot = j * kLdsStride + j;
 
-  // velocities of one cell: lane (g, j < D) holds component j of the gas
-  // (v0) and of species rows 4 v + g (x[v])
-  auto load_v = [&](int64_t cell, double& v0, double (&x)[4]) {
-    v0 = 0.0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = 0.0;
-    if (j < D && cell < A.n_cells) {
-      v0 = A.v_in[(int64_t)(j * n1) * ld + cell];
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (4 * v + g < N) x[v] = A.v_in[(int64_t)(j * n1 + 1 + 4 * v + g) * ld + cell];
-    }
-  };
-  double v0n, xn[4];
-  load_v(c0, v0n, xn);
+  // the quad's velocities through LDS: rows (component, species) x 4
+  // consecutive cells, loaded and stored with 4 lanes per 32-byte row piece.
+  // All loads precede all stores, so v_out may alias v_in.
+  double* vs = qp + 64;
+  const int rows = D * n1;
+  for (int f = lane; f < 4 * rows; f += 64) {
+    const int64_t cell = c0 + (f & 3);
+    vs[f] = cell < A.n_cells ? A.v_in[(int64_t)(f >> 2) * ld + cell] : 0.0;
+  }
+  __builtin_amdgcn_wave_barrier();
 
 #pragma unroll 1
   for (int c = 0; c < 4; ++c) {
     const int64_t cell = c0 + c;
     if (cell >= A.n_cells) break;  // uniform
-    const double v0 = v0n;
-    double x[4];
+    // lane (g, j < D): component j of the gas (v0) and of species rows 4 v + g
+    // (x[v]); read again at the apply rather than kept through the squarings
+    auto read_v = [&](double& v0, double (&x)[4]) {
+      v0 = 0.0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = xn[v];
-    if (c < 3) load_v(cell + 1, v0n, xn);  // prefetch the next cell
+      for (int v = 0; v < 4; ++v) x[v] = 0.0;
+      if (j < D) {
+        v0 = vs[(j * n1) * 4 + c];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (4 * v + g < N) x[v] = vs[(j * n1 + 1 + 4 * v + g) * 4 + c];
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    double v0, x[4];
+    read_v(v0, x);
 
-    unsigned cbad = (unsigned)__builtin_amdgcn_readlane((int)bad, 16 * c);
+    unsigned cbad = c == 0 ? bad_s[0] : c == 1 ? bad_s[1] : c == 2 ? bad_s[2] : bad_s[3];
     bool vfin = isfinite(v0);
 #pragma unroll
     for (int v = 0; v < 4; ++v) vfin = vfin && isfinite(x[v]);
     if (!__all(vfin) && !cbad) cbad = kBadVelocity;
     if (cbad) {
-      if (lane < D * n1) A.v_out[(int64_t)lane * ld + cell] = __builtin_nan("");
+      if (lane < rows) vs[lane * 4 + c] = __builtin_nan("");
       if (lane == 0) atomicOr(&g_status_word, cbad);
+      __builtin_amdgcn_wave_barrier();
       continue;
     }
-    const int kp = __builtin_amdgcn_readlane(kpack, 16 * c);
+    const int kp = c == 0 ? kp_s[0] : c == 1 ? kp_s[1] : c == 2 ? kp_s[2] : kp_s[3];
     const int kk = kp & 15, s = kp >> 4;
-    const int q = kTabQ[kk], r = kTabR[kk];
-    const double crsig = readlane_f64(rsig, 16 * c);
+    const int q = kPsQ[kk], r = kPsR[kk], m = kTabM[kk];
+    const double crsig = c == 0 ? rsig_s[0] : c == 1 ? rsig_s[1] : c == 2 ? rsig_s[2] : rsig_s[3];
 
     // scaled coefficients of this cell
     QuadRows R;
@@ -363,11 +391,10 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
     }
     v4d Z;
     switch (q) {  // uniform; one code path per power count
-      case 1: Z = quad_poly<1>(M, R, rm, r, stage, g, j); break;
-      case 2: Z = quad_poly<2>(M, R, rm, r, stage, g, j); break;
-      case 3: Z = quad_poly<3>(M, R, rm, r, stage, g, j); break;
-      case 4: Z = quad_poly<4>(M, R, rm, r, stage, g, j); break;
-      default: Z = quad_poly<5>(M, R, rm, r, stage, g, j); break;
+      case 2: Z = quad_poly<2>(M, R, rm, m, r, stage, g, j); break;
+      case 3: Z = quad_poly<3>(M, R, rm, m, r, stage, g, j); break;
+      case 4: Z = quad_poly<4>(M, R, rm, m, r, stage, g, j); break;
+      default: Z = quad_poly<5>(M, R, rm, m, r, stage, g, j); break;
     }
 
     // squarings Z <- (Z + 2 I) Z, two per trip so that the result and
@@ -381,6 +408,7 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
 
     // u = Z dv for every component at once (B operand: lane (g, j < D) holds
     // the relative velocities of rows 4 t + g, component j)
+    read_v(v0, x);
     double Bd[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) Bd[t] = (j < D && 4 * t + g < N) ? x[t] - v0 : 0.0;
@@ -397,23 +425,50 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
     if (j < D) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        if (4 * v + g < N) A.v_out[(int64_t)(j * n1 + 1 + 4 * v + g) * ld + cell] = x[v] + (d0 + U[v]);
+        if (4 * v + g < N) vs[(j * n1 + 1 + 4 * v + g) * 4 + c] = x[v] + (d0 + U[v]);
       }
-      if (g == 0) A.v_out[(int64_t)(j * n1) * ld + cell] = v0 + d0;
+      if (g == 0) vs[(j * n1) * 4 + c] = v0 + d0;
     }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (!store) return;
+  for (int f = lane; f < 4 * rows; f += 64) {
+    const int64_t cell = c0 + (f & 3);
+    if (cell < A.n_cells) A.v_out[(int64_t)(f >> 2) * ld + cell] = vs[f];
+  }
+}
+
+// Offset of the velocity block inside a quad's LDS block.
+constexpr int kQuadVelOffset = kStageDoubles + 3 * 64;
+
+// The workgroup's 16 cells g0 .. g0+15 (quads of its four wavefronts, in
+// order) stored from LDS a full 128-byte row piece at a time, so that every
+// output cache line is written whole by one store instruction.  Call after a
+// barrier that follows every wavefront's wave_forward_quad(store = false).
+__device__ __forceinline__ void group_store(const CellArgs& A, const int N, int64_t g0,
+                                            const double* lds) {
+  const int rows = A.n_dim * (N + 1);
+  for (int f = threadIdx.x; f < 16 * rows; f += 256) {
+    const int row = f >> 4, cell = f & 15;
+    if (g0 + cell < A.n_cells)
+      A.v_out[(int64_t)row * A.ld + g0 + cell] =
+          lds[(cell >> 2) * kQuadDoubles + kQuadVelOffset + row * 4 + (cell & 3)];
   }
 }
 
 template <int N>
-__global__ void __launch_bounds__(256) k_forward_wave(CellArgs A, int xcd_blocks) {
+__global__ void __launch_bounds__(256, 5) k_forward_wave(CellArgs A, int xcd_blocks) {
   __shared__ double lds[4 * kQuadDoubles];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int bid = blockIdx.x;
   const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
-  const int64_t c0 = (logical * 4 + w) * 4;
-  if (c0 >= A.n_cells) return;  // uniform over the wavefront
-  wave_forward_quad(A, N, c0, lane, lds + w * kQuadDoubles);
+  const int64_t g0 = logical * 16;  // the workgroup's first cell
+  if (g0 >= A.n_cells) return;     // uniform over the workgroup
+  const int64_t c0 = g0 + 4 * w;
+  if (c0 < A.n_cells) wave_forward_quad(A, N, c0, lane, lds + w * kQuadDoubles, false);
+  __syncthreads();
+  group_store(A, N, g0, lds);
 }
 
 }  // namespace dragexp
