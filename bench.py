@@ -140,6 +140,10 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="time the fused forward + adjoint (drag_expm_apply_backward) on the "
                          "workload instead of the forward (for profiling the adjoint kernels)")
+    ap.add_argument("--report", action="store_true",
+                    help="every workload configuration: GPU rate, roofline fractions, and the "
+                         "oracle beside it (1-core and all-core rates, errors on the same "
+                         "sample); one JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times), the "
                          "reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -166,6 +170,9 @@ def main():
         return
 
     name = args.workload
+    if args.report:
+        print(json.dumps(config_report(torch, ops, _lib, workloads, dev)), flush=True)
+        return
     if args.adjoint:
         print(json.dumps(adjoint_only(torch, ops, _lib, workloads, dev, name, args)), flush=True)
         return
@@ -259,6 +266,130 @@ def _time(torch, fn, steps, warmup):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def _oracle_rates(d, sample, threads):
+    """Oracle (CPU leg) on the first `sample` cells: its outputs, the
+    single-thread rate, and the rate with `threads` threads over chunks (the
+    oracle is a C library; ctypes releases the GIL during each call)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
+    sl = slice(0, sample)
+    args = (d["rho_g"][sl], d["rho_d"][:, sl], d["t_stop"][:, sl], d["v"][:, :, sl], d["dt"])
+    t0 = time.perf_counter()
+    ref, _, nrm, _ = oracle.apply_cells(*args)
+    t1 = time.perf_counter() - t0
+    bounds = np.linspace(0, sample, 4 * threads + 1).astype(int)
+    chunks = [slice(a, b) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+
+    def run(c):
+        oracle.apply_cells(d["rho_g"][c], d["rho_d"][:, c], d["t_stop"][:, c], d["v"][:, :, c],
+                           d["dt"])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, chunks))
+    tp = time.perf_counter() - t0
+    return ref, nrm, sample / t1, sample / tp
+
+
+def _err_stats(got, ref, v):
+    scale = np.abs(v).max(axis=1)
+    scale = np.where(scale == 0, 1.0, scale)
+    e = (np.abs(got - ref).max(axis=1) / scale).max(axis=0)
+    return {"max": float(e.max()), "p99.9": float(np.quantile(e, 0.999)),
+            "median": float(np.median(e))}
+
+
+def config_report(torch, ops, _lib, workloads, dev):
+    """All five workload configurations on one GPU, with the oracle timed
+    beside the GPU on a bounded sample of the same cells (single thread and
+    all cores) and the GPU's per-cell errors against it on that sample
+    (error of a cell: max over components and species of |dv'| / ||v_in||_inf)."""
+    threads = min(16, len(os.sched_getaffinity(0)))
+    out = {"threads": threads}
+    for cfg, name, sample in ((1, "n1_closed_form", 4096), (2, "n4_3d", 1 << 16),
+                              (3, "n16_stiff_3d", 1 << 13), (5, "n8_adjoint_3d", 1 << 15)):
+        d = workloads.make(name)
+        C, N, D = d["rho_g"].shape[0], d["rho_d"].shape[0], d["v"].shape[0]
+        T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
+        o = torch.empty_like(T["v"])
+        ms = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                 d["dt"], out=o), 50, 5)
+        got = o.cpu().numpy()
+        _, _, _, kk, mm, ss = ops.build(T["rho_g"], T["rho_d"], T["t_stop"], d["dt"])
+        kk, mm, ss = (x.cpu().numpy() for x in (kk, mm, ss))
+        f_alg = float(algorithmic_flops(kk, mm, ss, N, D).sum())
+        ref, nrm, r1, rp = _oracle_rates(d, min(sample, C), threads)
+        row = {"workload": name, "cells": C, "ms": ms, "cells_per_s": C / (ms * 1e-3),
+               "fp64_frac": f_alg / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+               "hbm_frac": algorithmic_bytes(C, N, D) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "err_vs_oracle": _err_stats(got[..., :ref.shape[-1]], ref, d["v"][..., :ref.shape[-1]]),
+               "oracle_sample": int(ref.shape[-1]), "oracle_1core_cells_per_s": r1,
+               "oracle_all_cores_cells_per_s": rp}
+        if cfg == 5:
+            dd = workloads.make(name, with_weights=True)
+            Tw = torch.from_numpy(dd["w"]).to(dev)
+            row["fwd_bwd_ms"] = _time(torch, lambda: ops.expm_apply_backward(
+                T["rho_g"], T["rho_d"], T["t_stop"], T["v"], Tw, d["dt"]), 20, 3)
+        out[f"config{cfg}"] = row
+    # config 4: the batched launch; the oracle on the first 32 blocks
+    batch = workloads.make_batched()
+    plan = ops.BatchPlan(batch["n_species"], batch["block_cells"], 3, batch["dt"])
+    fields, v = plan.pack(batch["blocks"], dev)
+    vo = torch.empty_like(v)
+    plan.autotune(fields, v, vo)
+    ms = _time(torch, lambda: plan.apply(fields, v, vo), 20, 3)
+    cells = len(batch["blocks"]) * batch["block_cells"]
+    # algorithmic work: the blocks of each N concatenated, (k*, m*, s*) from drag_build
+    f_alg = 0.0
+    for N in range(1, 17):
+        bl = [blk for blk, n in zip(batch["blocks"], batch["n_species"]) if n == N]
+        if not bl:
+            continue
+        cat = {k: np.concatenate([x[k] for x in bl], -1) for k in ("rho_g", "rho_d", "t_stop")}
+        kk, mm, ss = _lib_select_cells(ops, cat, batch["dt"], dev)
+        f_alg += float(algorithmic_flops(kk, mm, ss, N, 3).sum())
+    # the oracle on the first 32 blocks: one thread, then one block per thread
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    sample = batch["blocks"][:32]
+
+    def run(blk):
+        return oracle.apply_cells(blk["rho_g"], blk["rho_d"], blk["t_stop"], blk["v"], batch["dt"])
+
+    t0 = time.perf_counter()
+    refs = [run(blk) for blk in sample]
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, sample))
+    tp = time.perf_counter() - t0
+    errs = []
+    for b, (blk, r) in enumerate(zip(sample, refs)):
+        got = plan.block_view(vo, b).cpu().numpy()
+        scale = np.abs(blk["v"]).max(axis=1)
+        errs.append((np.abs(got - r[0]).max(axis=1) / np.where(scale == 0, 1, scale)).max(axis=0))
+    e = np.concatenate(errs)
+    plan.close()
+    out["config4"] = {"workload": "batched 4096 x 512, N_b ~ U{1..16}", "cells": cells, "ms": ms,
+                      "cells_per_s": cells / (ms * 1e-3),
+                      "fp64_frac": f_alg / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                      "err_vs_oracle": {"max": float(e.max()), "p99.9": float(np.quantile(e, 0.999)),
+                                        "median": float(np.median(e))},
+                      "oracle_sample": int(e.size),
+                      "oracle_1core_cells_per_s": e.size / t1,
+                      "oracle_all_cores_cells_per_s": e.size / tp}
+    return out
+
+
+def _lib_select_cells(ops, blk, dt, dev):
+    """(k*, m*, s*) of a block's cells from drag_build."""
+    import torch
+    T = {k: torch.from_numpy(np.ascontiguousarray(blk[k])).to(dev) for k in ("rho_g", "rho_d", "t_stop")}
+    _, _, _, k, m, s = ops.build(T["rho_g"], T["rho_d"], T["t_stop"], dt)
+    return k.cpu().numpy(), m.cpu().numpy(), s.cpu().numpy()
 
 
 def adjoint_only(torch, ops, _lib, workloads, dev, name, args):
