@@ -63,6 +63,7 @@ extern "C" {
 #define DRAG_ERR_NULL_POINTER  -9  /* a required array pointer is NULL (n_cells > 0) */
 #define DRAG_ERR_ALIAS        -10  /* an output overlaps an input it may not alias */
 #define DRAG_ERR_PLAN         -11  /* invalid batched plan or block table */
+#define DRAG_ERR_STEPS        -12  /* n_steps < 0 (drag_expm_steps) */
 #define DRAG_ERR_HIP          -20  /* the HIP runtime reported an error */
 
 /* per-cell bits of the sticky device status word */
@@ -115,6 +116,23 @@ int drag_build(const drag_desc *desc, const double *rho_g, const double *rho_d,
 int drag_expm_apply(const drag_desc *desc, const double *rho_g,
                     const double *rho_d, const double *t_stop,
                     const double *v_in, double *v_out, drag_stream_t stream);
+
+/*
+ * drag_expm_steps -- n_steps successive drag steps of the same dt, as a time
+ * integration of the drag ODE alone (the Collisions test of Sect. 3: gas
+ * and dust relaxing toward the common centre-of-mass velocity), each step
+ * the drag_expm_apply update of the state the previous step left:
+ *     v_out = E^n_steps v_in,  E = the approximant of exp(dt K).
+ *   history [n_steps][D][N+1][ld] or NULL: the state after every step
+ *           (history[i] after step i + 1); must not overlap any other array.
+ * v_out may equal v_in.  n_steps = 0 copies v_in to v_out.  The steps are
+ * n_steps launches on `stream` (no synchronisation); DRAG_ERR_STEPS for
+ * n_steps < 0.
+ */
+int drag_expm_steps(const drag_desc *desc, const double *rho_g,
+                    const double *rho_d, const double *t_stop,
+                    const double *v_in, double *v_out, int64_t n_steps,
+                    double *history, drag_stream_t stream);
 
 /*
  * drag_expm_apply_backward -- the adjoint of drag_expm_apply for the loss

@@ -606,6 +606,50 @@ int drag_expm_apply(const drag_desc* d, const double* rho_g, const double* rho_d
                               : wave_fwd((int)N)(A, (hipStream_t)stream);
 }
 
+int drag_expm_steps(const drag_desc* d, const double* rho_g, const double* rho_d,
+                    const double* t_stop, const double* v_in, double* v_out, int64_t n_steps,
+                    double* history, drag_stream_t stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (n_steps < 0) return DRAG_ERR_STEPS;
+  if (d->n_cells == 0 || n_steps == 0) {
+    if (d->n_cells && n_steps == 0 && (const double*)v_out != v_in) {
+      if (!v_in || !v_out) return DRAG_ERR_NULL_POINTER;
+      // zero steps: v_out = v_in
+      drag_desc one = *d;
+      one.dt = 0.0;  // the exact identity, bit for bit
+      return drag_expm_apply(&one, rho_g, rho_d, t_stop, v_in, v_out, stream);
+    }
+    return DRAG_OK;
+  }
+  if (!rho_g || !rho_d || !t_stop || !v_in || !v_out) return DRAG_ERR_NULL_POINTER;
+  const int64_t C = d->n_cells, ld = d->ld, N = d->n_species, D = d->n_dim;
+  const int64_t slab = D * (N + 1) * ld;  // elements of one velocity state
+  if (history) {
+    if (n_steps > INT64_MAX / slab) return DRAG_ERR_STEPS;
+    const Range rh{(uintptr_t)history, (uintptr_t)(history + n_steps * slab)};
+    if (overlap(rh, span(rho_g, 1, ld, C)) || overlap(rh, span(rho_d, N, ld, C)) ||
+        overlap(rh, span(t_stop, N, ld, C)) || overlap(rh, span(v_in, D * (N + 1), ld, C)) ||
+        overlap(rh, span(v_out, D * (N + 1), ld, C)))
+      return DRAG_ERR_ALIAS;
+  }
+  // step i reads the state after step i - 1 and writes history[i] (or v_out)
+  const double* src = v_in;
+  for (int64_t i = 0; i < n_steps; ++i) {
+    double* dst = history ? history + i * slab : v_out;
+    rc = drag_expm_apply(d, rho_g, rho_d, t_stop, src, dst, stream);
+    if (rc) return rc;
+    src = dst;
+  }
+  if (history) {
+    const size_t bytes = sizeof(double) * (size_t)((D * (N + 1) - 1) * ld + C);
+    if (hipMemcpyAsync(v_out, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream) !=
+        hipSuccess)
+      return DRAG_ERR_HIP;
+  }
+  return DRAG_OK;
+}
+
 int drag_expm_apply_backward(const drag_desc* d, const double* rho_g, const double* rho_d,
                              const double* t_stop, const double* v_in, const double* w,
                              double* v_out, double* g_v, double* g_logt, double* g_t,
@@ -779,6 +823,7 @@ const char* drag_status_string(int code) {
     case DRAG_ERR_N_CELLS: return "n_cells < 0";
     case DRAG_ERR_N_SPECIES: return "n_species outside [1, 16]";
     case DRAG_ERR_N_DIM: return "n_dim outside [1, 3]";
+    case DRAG_ERR_STEPS: return "n_steps < 0, or the history would overflow 64-bit offsets";
     case DRAG_ERR_LD: return "ld < n_cells or ld too large";
     case DRAG_ERR_DT: return "dt is NaN, infinite or negative";
     case DRAG_ERR_K_MAX: return "k_max outside [1, 9]";

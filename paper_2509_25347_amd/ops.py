@@ -89,6 +89,25 @@ def expm_apply(rho_g, rho_d, t_stop, v, dt, k_max=9, option=2, out=None, stream=
     return out
 
 
+def expm_steps(rho_g, rho_d, t_stop, v, dt, n_steps, history=False, k_max=9, option=2,
+               stream=None):
+    """n_steps drag steps of size dt (drag_expm_steps).  Returns v after the
+    last step, and with ``history`` also the [n_steps, D, N+1, C] states
+    after every step."""
+    C, N, D, ld = _shapes(rho_g, rho_d, t_stop, v)
+    if ld != C or not v.is_contiguous():
+        raise ValueError("expm_steps takes a contiguous v")
+    out = torch.empty_like(v)
+    hist = (torch.empty((int(n_steps),) + tuple(v.shape), dtype=torch.float64, device=v.device)
+            if history else None)
+    desc = _lib.make_desc(C, N, D, ld, dt, k_max, option)
+    _lib.check(_lib.lib().drag_expm_steps(ctypes.byref(desc), _ptr(rho_g), _ptr(rho_d),
+                                          _ptr(t_stop), _ptr(v), _ptr(out), int(n_steps),
+                                          _ptr(hist) if hist is not None and n_steps else None,
+                                          _stream_ptr(stream)), "drag_expm_steps")
+    return (out, hist) if history else out
+
+
 def build(rho_g, rho_d, t_stop, dt, k_max=9, option=2, stream=None):
     """Per-cell a = dt/t, e = rho_i/rho_g, ||dt K||_1 and (k*, m*, s*)."""
     for x, n in ((rho_g, "rho_g"), (rho_d, "rho_d"), (t_stop, "t_stop")):

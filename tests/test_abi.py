@@ -146,3 +146,11 @@ def test_mapping_controls(L):
         _lib.set_mapping(12, _lib.MAP_LANE)
     with pytest.raises(_lib.DragError):
         _lib.set_mapping(0, _lib.MAP_WAVE)
+
+
+def test_expm_steps_argument_errors(L):
+    """drag_expm_steps rejects a negative step count before touching the GPU."""
+    d = _lib.make_desc(0, 2, 1, 1, 0.1, 9, 2)
+    assert L.drag_expm_steps(ctypes.byref(d), None, None, None, None, None, -1, None, None) == _lib.ERR_STEPS
+    assert L.drag_expm_steps(ctypes.byref(d), None, None, None, None, None, 5, None, None) == _lib.OK
+    assert L.drag_expm_steps(None, None, None, None, None, None, 1, None, None) == _lib.ERR_NULL_DESC
