@@ -21,7 +21,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "truth.c")]
+_SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "truth.c"),
+            os.path.join(_HERE, "rk1.c")]
 
 BAD_DENSITY = 1
 BAD_STOPPING_TIME = 2
@@ -74,6 +75,8 @@ def _load():
     lib.orc_grad_cells.argtypes = [i64, i, i, i64, d, i, i, vp, vp, vp, vp, vp,
                                    vp, vp, vp, vp, vp]
     lib.orc_grad_cells.restype = i
+    lib.orc_rk1_cells.argtypes = [i64, i, i, i64, d, vp, vp, vp, vp, vp]
+    lib.orc_rk1_cells.restype = i
     lib.truth_expm_eigen.argtypes = [i, d, d, vp, vp, vp]
     lib.truth_expm_eigen.restype = i
     lib.truth_expm_taylor.argtypes = [i, vp, i, vp]
@@ -256,3 +259,17 @@ def grad_cells(rho_g, rho_d, t_stop, v, w, dt, K=9, option=2):
     if st < 0:
         raise ValueError("orc_grad_cells rejected its arguments (%d)" % st)
     return v_out, g_v, g_logt, g_rho_d, g_rho_g, st
+
+
+def rk1_cells(rho_g, rho_d, t_stop, v, dt):
+    """The implicit RK1 drag step v' = (I - dt K)^{-1} v for every cell
+    (dense Gaussian elimination; rk1.c).  Returns (v_out, status bits)."""
+    lib = _load()
+    rho_g, rho_d, t_stop, v = (_f64(x) for x in (rho_g, rho_d, t_stop, v))
+    D, n, C = v.shape
+    out = np.empty_like(v)
+    st = lib.orc_rk1_cells(C, n - 1, D, C, float(dt), _ptr(rho_g), _ptr(rho_d), _ptr(t_stop),
+                           _ptr(v), _ptr(out))
+    if st < 0:
+        raise ValueError("orc_rk1_cells: bad arguments")
+    return out, st

@@ -42,6 +42,10 @@ int orc_grad_cells(int64_t C, int N, int D, int64_t ld, double dt, int K,
                    double *g_rho_d, double *g_rho_g);
 
 /* independent truths, long double (truth.c) */
+/* rk1.c: the implicit RK1 drag step v' = (I - dt K)^{-1} v (dense solve) */
+int orc_rk1_cells(int64_t C, int N, int D, int64_t ld, double dt,
+                  const double *rho_g, const double *rho_d,
+                  const double *t_stop, const double *v_in, double *v_out);
 int truth_expm_eigen(int N, double dt, double rho_g, const double *rho_d,
                      const double *t_stop, double *E);
 int truth_expm_taylor(int n, const double *A, int terms, double *E);
