@@ -5,15 +5,17 @@
  *     (I - dt K) v' = v
  * per cell and velocity component (the linear system of the paper's
  * appendix on implicit solvers, eq. analytic_1, written for velocities).
- * The oracle is that definition: the dense (N+1) x (N+1) matrix I - dt K
- * built from orc_build's dt K, solved by Gaussian elimination with partial
- * pivoting.  Any elimination order subtracts nearly equal numbers when the
- * identity is tiny against dt K (stiff cells: the Schur complement of the
- * gas row is 1 + sum_i p_i / (1 + a_i), formed from terms of size sum_i p_i),
- * so the forward error is about u cond(I - dt K), 1e6 and more here.  The
- * elimination therefore runs in binary128 (__float128, u = 2^-113) and the
- * result is rounded once to double: the oracle is the exact solution of the
- * system to the last bit.
+ * The oracle is that definition: the dense (N+1) x (N+1) matrix I - dt K,
+ * solved by Gaussian elimination with partial pivoting, all in binary128
+ * (__float128, u = 2^-113) and rounded once to double.  The matrix is built
+ * in binary128 from the inputs themselves (a_i = dt / t_i, e_i = rho_i /
+ * rho_g, p_i = e_i a_i, the gas diagonal -sum_i p_i), not from dt K rounded
+ * to double: in a stiff cell a double A00 is off by u sum_i p_i, which moves
+ * the conserved mode of the solution by about u ||dt K|| (1e-10 at
+ * ||dt K|| = 1e6), and any elimination in double loses u cond(I - dt K) the
+ * same way.  With the exact entries the oracle is the solution of the
+ * backward Euler step itself, conserving rho_g v_g + sum_i rho_i v_i to the
+ * last bit.  Bad cells are detected by orc_build, as for the exponential.
  * The O(N) closed form the paper derives for this arrowhead system is what
  * the GPU kernel computes; it is not used here.
  */
@@ -68,7 +70,7 @@ int orc_rk1_cells(int64_t C, int N, int D, int64_t ld, double dt,
     const int n = N + 1;
     if (n > ORC_NMAX || D < 1 || D > 3 || ld < C) return -1;
     double A[ORC_NMAX * ORC_NMAX];
-    quad M[ORC_NMAX * ORC_NMAX], x[ORC_NMAX];
+    quad M[ORC_NMAX * ORC_NMAX], x[ORC_NMAX], qa[ORC_NMAX], qp[ORC_NMAX];
     double rd[ORC_NMAX], ts[ORC_NMAX], a[ORC_NMAX], e[ORC_NMAX];
     int status = 0;
     for (int64_t c = 0; c < C; ++c) {
@@ -85,11 +87,21 @@ int orc_rk1_cells(int64_t C, int N, int D, int64_t ld, double dt,
             for (int j = 0; j < n; ++j) x[j] = v_in[(d * n + j) * ld + c];
             int ok = !bad;
             if (ok) {
-                /* I - dt K from the doubles of dt K (a_i, p_i as the method
-                 * rounds them), then exact in binary128 */
-                for (int i = 0; i < n; ++i)
-                    for (int j = 0; j < n; ++j)
-                        M[i * n + j] = (quad)(i == j ? 1.0 : 0.0) - (quad)A[i * n + j];
+                /* I - dt K with the entries taken in binary128 from the
+                 * inputs (t_i = +inf gives a_i = 0) */
+                quad sp = 0;
+                for (int i = 0; i < N; ++i) {
+                    qa[i] = (quad)dt / (quad)ts[i];
+                    qp[i] = (quad)rd[i] / (quad)rho_g[c] * qa[i];
+                    sp += qp[i];
+                }
+                for (int k = 0; k < n * n; ++k) M[k] = 0;
+                M[0] = 1 + sp;
+                for (int i = 1; i < n; ++i) {
+                    M[i] = -qp[i - 1];
+                    M[i * n] = -qa[i - 1];
+                    M[i * n + i] = 1 + qa[i - 1];
+                }
                 ok = gauss_solve(n, M, x) == 0;
             }
             for (int j = 0; j < n; ++j) v_out[(d * n + j) * ld + c] = ok ? (double)x[j] : NAN;
