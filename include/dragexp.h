@@ -135,6 +135,24 @@ int drag_expm_steps(const drag_desc *desc, const double *rho_g,
                     double *history, drag_stream_t stream);
 
 /*
+ * drag_rk1_apply -- the first-order implicit (backward Euler) drag step, the
+ * cost and accuracy yardstick the paper compares the exponential with
+ * (Sect. 4, Fig. 6; appendix on implicit solvers, eqs. analytic_1 to
+ * analytic_4):
+ *     v_out = (I - dt K)^-1 v_in
+ * for every cell and velocity component, by the O(N) closed form of that
+ * arrowhead system (one cell per lane; bound by HBM bandwidth).  Same
+ * layout, aliasing rules, bad-cell flags and NaN outputs as drag_expm_apply;
+ * desc->k_max and desc->option are validated but not used.  dt = 0 returns v
+ * unchanged, bit for bit; a species with t_i = +inf keeps its velocity.
+ * The result is first-order accurate in dt (||v_out - exp(dt K) v_in|| is
+ * O(dt^2) per step) and relaxes to the barycentric velocity as dt/t_i grows.
+ */
+int drag_rk1_apply(const drag_desc *desc, const double *rho_g,
+                   const double *rho_d, const double *t_stop,
+                   const double *v_in, double *v_out, drag_stream_t stream);
+
+/*
  * drag_expm_apply_backward -- the adjoint of drag_expm_apply for the loss
  * L = sum_{d,j,c} grad_v_out[d][j][c] * v_out[d][j][c] (the chain rule of a
  * training step: grad_v_out = dL/dv_out).  The exponential is differentiated

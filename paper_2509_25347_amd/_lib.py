@@ -52,7 +52,7 @@ CELL_BAD_NORM = 8
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 
 EXPORTS = [
-    "drag_desc_init", "drag_build", "drag_expm_apply", "drag_expm_steps", "drag_expm_apply_backward",
+    "drag_desc_init", "drag_build", "drag_expm_apply", "drag_expm_steps", "drag_rk1_apply", "drag_expm_apply_backward",
     "drag_plan_batched", "drag_plan_offsets", "drag_expm_apply_batched",
     "drag_plan_autotune", "drag_plan_config", "drag_plan_set_config", "drag_plan_destroy", "drag_get_status", "drag_clear_status", "drag_status_string",
     "drag_table_row", "drag_select", "drag_set_mapping", "drag_get_mapping",
@@ -131,6 +131,8 @@ def lib():
     L.drag_expm_apply_batched.restype = ctypes.c_int
     L.drag_plan_autotune.argtypes = [vp, vp, vp, vp, vp, P(i32)]
     L.drag_plan_autotune.restype = ctypes.c_int
+    L.drag_rk1_apply.argtypes = [P(DragDesc), vp, vp, vp, vp, vp, vp]
+    L.drag_rk1_apply.restype = ctypes.c_int
     L.drag_expm_steps.argtypes = [P(DragDesc), vp, vp, vp, vp, vp, ctypes.c_int64, vp, vp]
     L.drag_expm_steps.restype = ctypes.c_int
     L.drag_plan_config.argtypes = [vp, P(i32), P(i32)]

@@ -19,6 +19,7 @@
 #include "adjoint.hpp"
 #include "pair.hpp"
 #include "batched.hpp"
+#include "rk1.hpp"
 
 namespace dragexp {
 
@@ -112,6 +113,13 @@ static int launch_forward_wave(const CellArgs& A, hipStream_t st) {
   return hip_status(hipGetLastError());
 }
 
+template <int N>
+static int launch_rk1(const CellArgs& A, hipStream_t st) {
+  const Grid gr = grid_for((A.n_cells + 255) / 256);
+  hipLaunchKernelGGL(k_rk1_lane<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
 using FwdFn = int (*)(const CellArgs&, hipStream_t);
 using BwdFn = int (*)(const BackArgs&, hipStream_t);
 
@@ -172,6 +180,15 @@ static FwdFn wave_fwd(int N) {
       launch_forward_wave<10>, launch_forward_wave<11>, launch_forward_wave<12>,
       launch_forward_wave<13>, launch_forward_wave<14>, launch_forward_wave<15>,
       launch_forward_wave<16>};
+  return tab[N - 1];
+}
+
+static FwdFn rk1_fwd(int N) {
+  static const FwdFn tab[16] = {
+      launch_rk1<1>,  launch_rk1<2>,  launch_rk1<3>,  launch_rk1<4>,
+      launch_rk1<5>,  launch_rk1<6>,  launch_rk1<7>,  launch_rk1<8>,
+      launch_rk1<9>,  launch_rk1<10>, launch_rk1<11>, launch_rk1<12>,
+      launch_rk1<13>, launch_rk1<14>, launch_rk1<15>, launch_rk1<16>};
   return tab[N - 1];
 }
 
@@ -604,6 +621,24 @@ int drag_expm_apply(const drag_desc* d, const double* rho_g, const double* rho_d
   const int map = mapping_for((int)N);
   return map == DRAG_MAP_LANE ? lane_fwd((int)N)(A, (hipStream_t)stream)
                               : wave_fwd((int)N)(A, (hipStream_t)stream);
+}
+
+int drag_rk1_apply(const drag_desc* d, const double* rho_g, const double* rho_d,
+                   const double* t_stop, const double* v_in, double* v_out,
+                   drag_stream_t stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (d->n_cells == 0) return DRAG_OK;
+  if (!rho_g || !rho_d || !t_stop || !v_in || !v_out) return DRAG_ERR_NULL_POINTER;
+  const int64_t C = d->n_cells, ld = d->ld, N = d->n_species, D = d->n_dim;
+  const Range ro = span(v_out, D * (N + 1), ld, C);
+  if (overlap(ro, span(rho_g, 1, ld, C)) || overlap(ro, span(rho_d, N, ld, C)) ||
+      overlap(ro, span(t_stop, N, ld, C)))
+    return DRAG_ERR_ALIAS;
+  if ((const double*)v_out != v_in && overlap(ro, span(v_in, D * (N + 1), ld, C)))
+    return DRAG_ERR_ALIAS;
+  CellArgs A{rho_g, rho_d, t_stop, v_in, v_out, C, ld, d->dt, (int)D, d->k_max, d->option};
+  return rk1_fwd((int)N)(A, (hipStream_t)stream);
 }
 
 int drag_expm_steps(const drag_desc* d, const double* rho_g, const double* rho_d,

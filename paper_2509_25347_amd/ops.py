@@ -89,6 +89,23 @@ def expm_apply(rho_g, rho_d, t_stop, v, dt, k_max=9, option=2, out=None, stream=
     return out
 
 
+def rk1_apply(rho_g, rho_d, t_stop, v, dt, out=None, stream=None):
+    """v' = (I - dt K)^-1 v for every cell, the first-order implicit drag step
+    by its O(N) closed form (drag_rk1_apply).  ``out`` may be ``v`` itself."""
+    C, N, D, ld = _shapes(rho_g, rho_d, t_stop, v)
+    if out is None:
+        out = torch.empty_like(v)
+    else:
+        _require(out, "out")
+        if out.shape != v.shape or _ld_of(out, 2, "out") not in (None, ld) and C:
+            raise ValueError("out must have the shape and layout of v")
+    desc = _lib.make_desc(C, N, D, ld, dt)
+    _lib.check(_lib.lib().drag_rk1_apply(ctypes.byref(desc), _ptr(rho_g), _ptr(rho_d),
+                                         _ptr(t_stop), _ptr(v), _ptr(out),
+                                         _stream_ptr(stream)), "drag_rk1_apply")
+    return out
+
+
 def expm_steps(rho_g, rho_d, t_stop, v, dt, n_steps, history=False, k_max=9, option=2,
                stream=None):
     """n_steps drag steps of size dt (drag_expm_steps).  Returns v after the

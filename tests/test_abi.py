@@ -28,7 +28,7 @@ def L():
 def _declared():
     src = open(os.path.join(ROOT, "include", "dragexp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(drag_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(drag_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol(L):
