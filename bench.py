@@ -73,7 +73,8 @@ def algorithmic_bytes(C, N, D):
 
 
 KERNEL_SOURCES = {"k_forward_wave": ("common.hpp", "wave.hpp"),
-                  "k_forward_lane": ("common.hpp", "lane.hpp")}
+                  "k_forward_lane": ("common.hpp", "lane.hpp"),
+                  "k_rk1_lane": ("common.hpp", "rk1.hpp")}
 
 
 def source_hash(kernel):
@@ -140,6 +141,9 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="time the fused forward + adjoint (drag_expm_apply_backward) on the "
                          "workload instead of the forward (for profiling the adjoint kernels)")
+    ap.add_argument("--rk1", action="store_true",
+                    help="time the backward Euler step (drag_rk1_apply) on the workload instead "
+                         "of the exponential, with its HBM roofline")
     ap.add_argument("--report", action="store_true",
                     help="every workload configuration: GPU rate, roofline fractions, and the "
                          "oracle beside it (1-core and all-core rates, errors on the same "
@@ -175,6 +179,9 @@ def main():
         return
     if args.adjoint:
         print(json.dumps(adjoint_only(torch, ops, _lib, workloads, dev, name, args)), flush=True)
+        return
+    if args.rk1:
+        print(json.dumps(rk1_only(torch, ops, workloads, dev, name, args)), flush=True)
         return
     d = workloads.make(name, args.cells)
     C = d["rho_g"].shape[0]
@@ -247,6 +254,7 @@ def main():
     if not args.no_comparisons:
         res["fwd_bwd_vs_fwd"] = adjoint_measurement(torch, ops, workloads, dev)
         res["batched_vs_plain"] = batched_measurement(torch, ops, workloads, dev)
+        res["rk1_vs_expm"] = rk1_measurement(torch, ops, workloads, dev)
     if args.extra:
         res["extra"] = extra_measurements(torch, ops, workloads, dev)
     if not args.no_cpu_baseline:
@@ -404,6 +412,55 @@ def adjoint_only(torch, ops, _lib, workloads, dev, name, args):
             "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": name, "n_cells": C, "n_species": N}}
+
+
+def rk1_roofline(ms, C, N, D, workload):
+    """HBM roofline of the backward Euler kernel: it moves the same bytes as
+    the exponential (read rho_g, rho_d, t_stop, v; write v')."""
+    b = algorithmic_bytes(C, N, D)
+    gbs = b / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": profiled_traffic("k_rk1_lane", workload),
+            "kernel": f"k_rk1_lane<{N}>", "hbm_bytes_per_launch": b}
+
+
+def rk1_only(torch, ops, workloads, dev, name, args):
+    """The backward Euler step alone on one workload (for profiling k_rk1_lane)."""
+    d = workloads.make(name, args.cells)
+    T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
+    out = torch.empty_like(T["v"])
+    C, N, D = d["rho_g"].shape[0], d["rho_d"].shape[0], d["v"].shape[0]
+    ms = _time(torch, lambda: ops.rk1_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"],
+                                            out=out), args.steps, args.warmup)
+    return {"metric": "FP64 backward Euler cell-updates/s", "value": C / (ms * 1e-3),
+            "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": name, "n_cells": C, "n_species": N, "n_dim": D},
+            "roofline": rk1_roofline(ms, C, N, D, name)}
+
+
+def rk1_measurement(torch, ops, workloads, dev, names=("n16_stiff_3d", "n8_adjoint_3d", "n4_3d")):
+    """The paper's yardstick beside the exponential: the backward Euler step
+    (drag_rk1_apply) on the same cells, its HBM roofline, the time ratio
+    EXP / RK1, and how far one RK1 step lands from exp(dt K) v (per cell:
+    max |v'_rk1 - v'_exp| / ||v||_inf; median and max over the cells)."""
+    res = {}
+    for name in names:
+        d = workloads.make(name)
+        C, N, D = d["rho_g"].shape[0], d["rho_d"].shape[0], d["v"].shape[0]
+        T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
+        o1, o2 = torch.empty_like(T["v"]), torch.empty_like(T["v"])
+        t_rk1 = _time(torch, lambda: ops.rk1_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                   d["dt"], out=o1), 30, 3)
+        t_exp = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                    d["dt"], out=o2), 20, 3)
+        scale = T["v"].abs().amax(dim=1)
+        gap = ((o1 - o2).abs().amax(dim=1) / scale).amax(dim=0)
+        res[name] = {"n_cells": C, "n_species": N, "rk1_ms": t_rk1, "expm_ms": t_exp,
+                     "expm_over_rk1": t_exp / t_rk1, "rk1_cells_per_s": C / (t_rk1 * 1e-3),
+                     "rk1_roofline": rk1_roofline(t_rk1, C, N, D, name),
+                     "rk1_step_gap_to_exp": {"median": float(gap.median()), "max": float(gap.max())}}
+    return res
 
 
 def adjoint_measurement(torch, ops, workloads, dev):

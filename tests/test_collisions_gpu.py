@@ -108,3 +108,42 @@ def test_collisions_against_table1_and_oracle(ops, case):
         v, _, _, st = oracle.apply_cells(rho_g, rho_d, t_stop, v, dt)
         assert st == 0
         assert np.abs(got[i] - v[0, :, 0]).max() <= 1e-13 * max(1.0, i)
+
+
+@pytest.mark.parametrize("case", ["B", "C"])
+def test_collisions_rk1_first_order(ops, case):
+    """The same sweep with the backward Euler step (drag_rk1_apply, stepped in
+    place): the trajectory follows the oracle's own RK1 integration to
+    rounding, Er_1 halves with Delta t (first order: ratios 1.98, 1.97, 1.94
+    for B and 1.98, 1.97, 1.93 for C over the first doublings), and it sits
+    ten orders of magnitude above the exponential's at every Delta t."""
+    import oracle
+    t = table1()[case]
+    rho_g, rho_d, t_stop, v0 = case_arrays(t)
+    dev = torch.device("cuda:0")
+    T = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (rho_g, rho_d, t_stop)]
+    dt0, t_final = SWEEP[case]
+    er1 = {}
+    for j in range(6):
+        dt = dt0 * 2 ** j
+        M = int(np.floor(t_final / dt * (1 + 1e-12)))
+        v = torch.from_numpy(v0.copy()).to(dev)
+        states = []
+        for i in range(M):
+            ops.rk1_apply(*T, v, dt, out=v)
+            states.append(v.clone())
+        got = torch.stack(states).cpu().numpy()[:, 0, :, 0]
+        ref = v0.copy()
+        err = 0.0
+        for i in range(M):
+            ref, st = oracle.rk1_cells(rho_g, rho_d, t_stop, ref, dt)
+            assert st == 0
+            assert np.abs(got[i] - ref[0, :, 0]).max() <= 32 * 2.0 ** -53 * 2 * (i + 1)
+            exact = oracle.truth_eigen((i + 1) * dt, rho_g[0], rho_d[:, 0], t_stop[:, 0]) @ v0[0, :, 0]
+            err += np.sum(np.abs(got[i] - exact) / np.abs(exact))
+        er1[dt] = err / M
+    print(f"RK1 Er_1 {case}: " + ", ".join(f"dt={k:.4g}: {v:.3g}" for k, v in er1.items()))
+    e = list(er1.values())
+    ratios = [e[i + 1] / e[i] for i in range(3)]
+    assert all(1.85 <= r <= 2.05 for r in ratios), ratios
+    assert min(e) >= 1e-5
