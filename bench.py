@@ -336,6 +336,10 @@ def config_report(torch, ops, _lib, workloads, dev):
                "err_vs_oracle": _err_stats(got[..., :ref.shape[-1]], ref, d["v"][..., :ref.shape[-1]]),
                "oracle_sample": int(ref.shape[-1]), "oracle_1core_cells_per_s": r1,
                "oracle_all_cores_cells_per_s": rp}
+        ms_auto = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                      d["dt"], k_max=_lib.K_AUTO, out=o), 50, 5)
+        row["taylor_cap_tuned"] = {"k_max": _lib.get_k_max(N), "ms": ms_auto,
+                                   "cells_per_s": C / (ms_auto * 1e-3), "speedup_vs_k9": ms / ms_auto}
         if cfg == 5:
             dd = workloads.make(name, with_weights=True)
             Tw = torch.from_numpy(dd["w"]).to(dev)
@@ -478,15 +482,12 @@ def adjoint_measurement(torch, ops, workloads, dev):
 
 def batched_measurement(torch, ops, workloads, dev):
     """The batched uneven-N graph against the plain per-N launches over the
-    same cells (blocks grouped by N into contiguous arrays)."""
+    same cells (blocks grouped by N into contiguous arrays), first with the
+    paper's K = 9 for every N, then with the Taylor cap tuned per N by the
+    plan's autotuner (the plain launches then use the same per-N caps)."""
     import numpy as np
+    from paper_2509_25347_amd import _lib
     batch = workloads.make_batched()
-    plan = ops.BatchPlan(batch["n_species"], batch["block_cells"], 3, batch["dt"])
-    fields, v = plan.pack(batch["blocks"], dev)
-    out = torch.empty_like(v)
-    plan.autotune(fields, v, out)
-    lane_max, mfma_mode = plan.config()
-    tb = _time(torch, lambda: plan.apply(fields, v, out), 10, 2)
     groups = {}
     for b, blk in enumerate(batch["blocks"]):
         groups.setdefault(int(batch["n_species"][b]), []).append(blk)
@@ -494,19 +495,35 @@ def batched_measurement(torch, ops, workloads, dev):
     for N, bl in sorted(groups.items()):
         cat = {k: torch.from_numpy(np.ascontiguousarray(np.concatenate([x[k] for x in bl], -1))).to(dev)
                for k in ("rho_g", "rho_d", "t_stop", "v")}
-        per.append((cat, torch.empty_like(cat["v"])))
-
-    def plain():
-        for cat, o in per:
-            ops.expm_apply(cat["rho_g"], cat["rho_d"], cat["t_stop"], cat["v"], batch["dt"], out=o)
-
-    tp = _time(torch, plain, 10, 2)
+        per.append((N, cat, torch.empty_like(cat["v"])))
     cells = len(batch["blocks"]) * batch["block_cells"]
-    plan.close()
-    return {"workload": "4096 blocks x 512 cells, N_b ~ U{1..16}, D = 3", "n_cells": cells,
-            "batched_ms": tb, "plain_per_n_ms": tp, "batched_over_plain": tb / tp,
-            "batched_cells_per_s": cells / (tb * 1e-3),
-            "lane_max": lane_max, "mfma_mode": mfma_mode}
+    res = {"workload": "4096 blocks x 512 cells, N_b ~ U{1..16}, D = 3", "n_cells": cells}
+    for label, k_req in (("k9", 9), ("k_auto", _lib.K_AUTO)):
+        plan = ops.BatchPlan(batch["n_species"], batch["block_cells"], 3, batch["dt"], k_max=k_req)
+        fields, v = plan.pack(batch["blocks"], dev)
+        out = torch.empty_like(v)
+        plan.autotune(fields, v, out)
+        lane_max, mfma_mode = plan.config()
+        ks = plan.k_max()
+        tb = _time(torch, lambda: plan.apply(fields, v, out), 10, 2)
+
+        def plain():
+            for N, cat, o in per:
+                ops.expm_apply(cat["rho_g"], cat["rho_d"], cat["t_stop"], cat["v"], batch["dt"],
+                               k_max=ks[N - 1], out=o)
+
+        tp = _time(torch, plain, 10, 2)
+        plan.close()
+        row = {"batched_ms": tb, "plain_per_n_ms": tp, "batched_over_plain": tb / tp,
+               "batched_cells_per_s": cells / (tb * 1e-3), "lane_max": lane_max,
+               "mfma_mode": mfma_mode}
+        if label == "k9":
+            res.update(row)
+        else:
+            row["k_max_per_n"] = ks
+            res["taylor_cap_tuned"] = row
+    res["taylor_cap_tuned"]["speedup_vs_k9"] = res["batched_ms"] / res["taylor_cap_tuned"]["batched_ms"]
+    return res
 
 
 def extra_measurements(torch, ops, workloads, dev):

@@ -58,7 +58,7 @@ extern "C" {
 #define DRAG_ERR_N_DIM         -4  /* n_dim outside [1, 3] */
 #define DRAG_ERR_LD            -5  /* ld < n_cells, or ld too large for 64-bit offsets */
 #define DRAG_ERR_DT            -6  /* dt NaN, infinite or < 0 */
-#define DRAG_ERR_K_MAX         -7  /* k_max outside [1, 9] */
+#define DRAG_ERR_K_MAX         -7  /* k_max outside [0, 9] */
 #define DRAG_ERR_OPTION        -8  /* option not 0, 1 or 2 */
 #define DRAG_ERR_NULL_POINTER  -9  /* a required array pointer is NULL (n_cells > 0) */
 #define DRAG_ERR_ALIAS        -10  /* an output overlaps an input it may not alias */
@@ -72,6 +72,9 @@ extern "C" {
 #define DRAG_CELL_BAD_VELOCITY      4
 #define DRAG_CELL_BAD_NORM          8
 
+/* k_max = DRAG_K_AUTO: the Taylor cap K is the library's per-N choice */
+#define DRAG_K_AUTO 0
+
 /* an opaque hipStream_t */
 typedef void *drag_stream_t;
 
@@ -81,7 +84,9 @@ typedef struct drag_desc {
     int32_t n_dim;     /* D in [1, 3] */
     int64_t ld;        /* leading dimension of every [.][ld] array, >= C */
     double dt;         /* finite, >= 0; dt = 0 returns v unchanged, bit for bit */
-    int32_t k_max;     /* K of Alg. 1, 1..9 (9: m up to 30, Table B.1) */
+    int32_t k_max;     /* K of Alg. 1, 1..9 (9: m up to 30, Table B.1), or
+                          DRAG_K_AUTO: the library's tuned K for n_species
+                          (drag_get_k_max) */
     int32_t option;    /* Alg. 1 option: 0 standard, 1, 2 (fewest products) */
 } drag_desc;
 
@@ -196,7 +201,9 @@ typedef struct drag_batch_desc {
     int32_t n_blocks;         /* >= 1 */
     int32_t block_cells;      /* cells per block, >= 1 */
     int32_t n_dim;            /* D in [1, 3] */
-    int32_t k_max;            /* 1..9 */
+    int32_t k_max;            /* 1..9 for every block, or DRAG_K_AUTO: per N,
+                                 drag_get_k_max at plan creation, then the
+                                 autotuner's choice (drag_plan_k_max) */
     int32_t option;           /* 0, 1, 2 */
     double dt;                /* finite, >= 0 */
     const int32_t *n_species; /* host array [n_blocks], each in [1, 16] */
@@ -217,7 +224,10 @@ int drag_expm_apply_batched(drag_plan *plan, const double *fields,
  * `stream`), keep the fastest, and report its lane-mapping bound: blocks
  * with N_b <= *lane_max_out run one cell per lane, the others on the FP64
  * MFMA path (a quad of cells per wavefront) in the form that timed fastest
- * (drag_plan_config).  The next drag_expm_apply_batched re-captures. */
+ * (drag_plan_config).  A DRAG_K_AUTO plan then also times each species
+ * count's launch for every Taylor cap K = 3..9 and keeps the fastest per N
+ * (drag_plan_k_max); v_out ends with the chosen configuration's result.
+ * The next drag_expm_apply_batched re-captures. */
 int drag_plan_autotune(drag_plan *plan, const double *fields,
                        const double *v_in, double *v_out,
                        drag_stream_t stream, int32_t *lane_max_out);
@@ -235,6 +245,10 @@ int drag_plan_config(const drag_plan *plan, int32_t *lane_max,
  * an mfma_mode above (DRAG_ERR_OPTION otherwise, the plan unchanged).  The
  * next drag_expm_apply_batched re-captures; results do not depend on it. */
 int drag_plan_set_config(drag_plan *plan, int32_t lane_max, int32_t mfma_mode);
+/* The Taylor cap K each species count runs with (k_max[N - 1], N = 1..16).
+ * A block of N_b species gives exactly drag_expm_apply's result with
+ * k_max = k_max[N_b - 1] and the same mapping. */
+int drag_plan_k_max(const drag_plan *plan, int32_t *k_max);
 int drag_plan_destroy(drag_plan *plan);
 
 /* ---- status and introspection -------------------------------------------- */
@@ -265,6 +279,15 @@ int drag_select(double norm, int32_t k_max, int32_t option, int32_t *k,
 #define DRAG_MAP_AUTO 0
 #define DRAG_MAP_LANE 1
 #define DRAG_MAP_WAVE 2
+/* The Taylor cap K that DRAG_K_AUTO stands for, per species count (host-side,
+ * per process).  Every K gives an approximant accurate to u (Alg. 1 keeps
+ * ||dt K / 2^s||_1 <= theta_m); K trades polynomial degree against
+ * squarings.  The defaults were measured on MI355X (2^18 cells per N): K = 3
+ * or 4 for N <= 4, 5 for N = 5-6, 6 for N = 7-8 (0.72-0.98 of the time at
+ * K = 9 on the one-lane kernel), 7 for N >= 9.  drag_set_k_max(N, 0)
+ * restores the default; DRAG_ERR_N_SPECIES / DRAG_ERR_K_MAX otherwise. */
+int drag_set_k_max(int32_t n_species, int32_t k_max);
+int drag_get_k_max(int32_t n_species, int32_t *k_max);
 int drag_set_mapping(int32_t n_species, int32_t mapping);
 int drag_get_mapping(int32_t n_species, int32_t *mapping);
 

@@ -50,12 +50,14 @@ CELL_BAD_VELOCITY = 4
 CELL_BAD_NORM = 8
 
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
+K_AUTO = 0
 
 EXPORTS = [
     "drag_desc_init", "drag_build", "drag_expm_apply", "drag_expm_steps", "drag_rk1_apply", "drag_expm_apply_backward",
     "drag_plan_batched", "drag_plan_offsets", "drag_expm_apply_batched",
     "drag_plan_autotune", "drag_plan_config", "drag_plan_set_config", "drag_plan_destroy", "drag_get_status", "drag_clear_status", "drag_status_string",
     "drag_table_row", "drag_select", "drag_set_mapping", "drag_get_mapping",
+    "drag_set_k_max", "drag_get_k_max", "drag_plan_k_max",
 ]
 
 
@@ -155,6 +157,12 @@ def lib():
     L.drag_set_mapping.restype = ctypes.c_int
     L.drag_get_mapping.argtypes = [i32, P(i32)]
     L.drag_get_mapping.restype = ctypes.c_int
+    L.drag_set_k_max.argtypes = [i32, i32]
+    L.drag_set_k_max.restype = ctypes.c_int
+    L.drag_get_k_max.argtypes = [i32, P(i32)]
+    L.drag_get_k_max.restype = ctypes.c_int
+    L.drag_plan_k_max.argtypes = [vp, P(i32)]
+    L.drag_plan_k_max.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -198,3 +206,15 @@ def get_mapping(n_species: int) -> int:
     m = ctypes.c_int32()
     check(lib().drag_get_mapping(n_species, ctypes.byref(m)), "drag_get_mapping")
     return m.value
+
+
+def set_k_max(n_species: int, k_max: int) -> None:
+    """Override the Taylor cap K that K_AUTO means for this N (0 restores)."""
+    check(lib().drag_set_k_max(n_species, k_max), "drag_set_k_max")
+
+
+def get_k_max(n_species: int) -> int:
+    """The Taylor cap K that K_AUTO means for this N."""
+    k = ctypes.c_int32()
+    check(lib().drag_get_k_max(n_species, ctypes.byref(k)), "drag_get_k_max")
+    return k.value

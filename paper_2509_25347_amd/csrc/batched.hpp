@@ -43,9 +43,9 @@ struct BatchArgs {
   int n_items;
   int block_cells;
   int n_dim;
-  int k_max;
   int option;
   double dt;
+  int k_max_n[kMaxSpecies + 1];  // Taylor cap K of Alg. 1 per species count (index N)
 };
 
 __global__ void k_batch_reset(unsigned int* counter) { *counter = 0u; }
@@ -62,7 +62,7 @@ __device__ __forceinline__ CellArgs block_args(const BatchArgs& B, const BatchIt
   A.ld = bc;
   A.dt = B.dt;
   A.n_dim = B.n_dim;
-  A.k_max = B.k_max;
+  A.k_max = B.k_max_n[it.n];
   A.option = B.option;
   return A;
 }

@@ -234,6 +234,25 @@ static int mapping_for_bwd(int N) {
   return m;
 }
 
+// Taylor cap K of Alg. 1 used when a descriptor asks for DRAG_K_AUTO (index
+// N - 1), overridable with drag_set_k_max.  Every K gives an approximant
+// accurate to u (the selection keeps ||A / 2^s|| <= theta_m); K only trades
+// polynomial degree against squarings.  The one-lane kernel evaluates the
+// polynomial by Horner in the structured matrix (m steps of O(N^2)) and
+// squares densely (O(N^3)), so small N prefers low degrees; the MFMA kernel
+// is flat for K >= 7.  Measured on MI355X over 2^18 cells per N (stiff and
+// jittered recipes), the fastest K against K = 9: N = 2-4 K = 3-4 (0.72-0.86
+// of the time), N = 5-6 K = 5 (0.83-0.92), N = 7-8 K = 6 (0.88-0.98),
+// N >= 9 K = 7 (0.98-0.99).
+static const int g_default_kmax[16] = {4, 3, 3, 4, 5, 5, 6, 6, 7, 7, 7, 7, 7, 7, 7, 7};
+static int g_kmax_override[16] = {0};
+
+static int k_for(int k_max, int N) {
+  if (k_max != DRAG_K_AUTO) return k_max;
+  const int o = g_kmax_override[N - 1];
+  return o ? o : g_default_kmax[N - 1];
+}
+
 // ---- argument checks -------------------------------------------------------------
 static int check_desc(const drag_desc* d) {
   if (!d) return DRAG_ERR_NULL_DESC;
@@ -244,7 +263,7 @@ static int check_desc(const drag_desc* d) {
   // every index (row * ld + c) must fit in int64 with room to spare
   if (d->ld > (INT64_MAX / 64)) return DRAG_ERR_LD;
   if (!(d->dt >= 0.0) || !isfinite(d->dt)) return DRAG_ERR_DT;
-  if (d->k_max < 1 || d->k_max > 9) return DRAG_ERR_K_MAX;
+  if (d->k_max < DRAG_K_AUTO || d->k_max > 9) return DRAG_ERR_K_MAX;
   if (d->option < 0 || d->option > 2) return DRAG_ERR_OPTION;
   return DRAG_OK;
 }
@@ -277,6 +296,9 @@ constexpr int kWavePersistent = 0;
 constexpr int kWaveGrid = 1;
 constexpr int kWavePerN = 2;
 constexpr int kWaveModes = 3;
+// smallest Taylor cap the plan's autotuner tries (K = 1, 2 cap m at 2 and 4:
+// every cell then needs many squarings)
+constexpr int kTuneKMin = 3;
 
 struct BatchVariant {
   int lmax = 6;
@@ -338,6 +360,7 @@ static void batched_lane(int N, const BatchArgs& B, hipStream_t st) {
 struct drag_plan {
   int device = 0;
   int n_blocks = 0, block_cells = 0, n_dim = 0, k_max = 9, option = 2;
+  int k_n[dragexp::kMaxSpecies + 1] = {};  // Taylor cap per N (index N)
   double dt = 0.0;
   std::vector<int32_t> n_species;
   std::vector<int64_t> field_off, v_off;
@@ -408,6 +431,7 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
   P->block_cells = bd->block_cells;
   P->n_dim = bd->n_dim;
   P->k_max = bd->k_max;
+  for (int n = 1; n <= kMaxSpecies; ++n) P->k_n[n] = k_for(bd->k_max, n);
   P->option = bd->option;
   P->dt = bd->dt;
   P->n_species.assign(bd->n_species, bd->n_species + bd->n_blocks);
@@ -491,7 +515,8 @@ static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
   while (v + 1 < kBatchVariants && kBatchLmax[v] != lmax) ++v;
   const BatchVariant& V = P->var[v];
   BatchArgs B{nullptr, P->d_field_off, P->d_v_off, fields, v_in, v_out, P->d_counter,
-              0,       P->block_cells, P->n_dim, P->k_max, P->option, P->dt};
+              0,       P->block_cells, P->n_dim, P->option, P->dt, {}};
+  for (int n = 0; n <= kMaxSpecies; ++n) B.k_max_n[n] = P->k_n[n];
   if (hipEventRecord(P->ev_fork, main) != hipSuccess) return DRAG_ERR_HIP;
   if (hipStreamWaitEvent(side, P->ev_fork, 0) != hipSuccess) return DRAG_ERR_HIP;
   for (int n = 1; n <= kLaneMaxN; ++n) {
@@ -596,7 +621,7 @@ int drag_build(const drag_desc* d, const double* rho_g, const double* rho_d,
     for (int y = x + 1; y < 6; ++y)
       if (overlap(out[x], out[y])) return DRAG_ERR_ALIAS;
   BuildArgs B{rho_g, rho_d, t_stop, a_out, e_out, norm_out, k_out, m_out, s_out,
-              C,     ld,    d->dt,  (int)N, d->k_max, d->option};
+              C,     ld,    d->dt,  (int)N, k_for(d->k_max, (int)N), d->option};
   const Grid gr = grid_for((C + 255) / 256);
   hipLaunchKernelGGL(k_build, dim3(gr.blocks), dim3(256), 0, (hipStream_t)stream, B,
                      gr.xcd_blocks);
@@ -617,7 +642,8 @@ int drag_expm_apply(const drag_desc* d, const double* rho_g, const double* rho_d
     return DRAG_ERR_ALIAS;
   if ((const double*)v_out != v_in && overlap(ro, span(v_in, D * (N + 1), ld, C)))
     return DRAG_ERR_ALIAS;
-  CellArgs A{rho_g, rho_d, t_stop, v_in, v_out, C, ld, d->dt, (int)D, d->k_max, d->option};
+  CellArgs A{rho_g, rho_d, t_stop, v_in, v_out, C,
+             ld,    d->dt, (int)D, k_for(d->k_max, (int)N), d->option};
   const int map = mapping_for((int)N);
   return map == DRAG_MAP_LANE ? lane_fwd((int)N)(A, (hipStream_t)stream)
                               : wave_fwd((int)N)(A, (hipStream_t)stream);
@@ -706,7 +732,7 @@ int drag_expm_apply_backward(const drag_desc* d, const double* rho_g, const doub
       if (overlap(out[x], out[y])) return DRAG_ERR_ALIAS;
   }
   BackArgs B{rho_g, rho_d, t_stop, v_in, w, v_out, g_v, g_logt, g_t, g_rho_d, g_rho_g,
-             C,     ld,    d->dt,  (int)D, d->k_max, d->option};
+             C,     ld,    d->dt,  (int)D, k_for(d->k_max, (int)N), d->option};
   const int map = mapping_for_bwd((int)N);
   return map == DRAG_MAP_LANE ? lane_bwd((int)N)(B, (hipStream_t)stream)
                               : wave_bwd((int)N)(B, (hipStream_t)stream);
@@ -719,7 +745,7 @@ int drag_plan_batched(const drag_batch_desc* bd, drag_plan** out) {
   if (bd->n_blocks < 1 || bd->block_cells < 1 || !bd->n_species) return DRAG_ERR_PLAN;
   if (bd->n_dim < 1 || bd->n_dim > 3) return DRAG_ERR_N_DIM;
   if (!(bd->dt >= 0.0) || !isfinite(bd->dt)) return DRAG_ERR_DT;
-  if (bd->k_max < 1 || bd->k_max > 9) return DRAG_ERR_K_MAX;
+  if (bd->k_max < DRAG_K_AUTO || bd->k_max > 9) return DRAG_ERR_K_MAX;
   if (bd->option < 0 || bd->option > 2) return DRAG_ERR_OPTION;
   for (int b = 0; b < bd->n_blocks; ++b)
     if (bd->n_species[b] < 1 || bd->n_species[b] > kMaxSpecies) return DRAG_ERR_N_SPECIES;
@@ -802,13 +828,69 @@ int drag_plan_autotune(drag_plan* P, const double* fields, const double* v_in, d
       }
     }
   }
+  if (!rc) {
+    P->lmax = best;
+    P->wave_mode = best_mode;
+  }
+  // Taylor cap per species count (a DRAG_K_AUTO plan only): each N's own
+  // launch (its lane grid, or its MFMA grid compiled for N) timed alone for
+  // every K; the per-cell code is the same in every MFMA form, so the choice
+  // carries over to the persistent and run-time-N grids.
+  if (!rc && P->k_max == DRAG_K_AUTO) {
+    int v = 0;
+    while (v + 1 < kBatchVariants && kBatchLmax[v] != P->lmax) ++v;
+    const BatchVariant& V = P->var[v];
+    const int gpb = (P->block_cells + 15) / 16;
+    BatchArgs B{nullptr, P->d_field_off, P->d_v_off, fields, v_in, v_out, P->d_counter,
+                0,       P->block_cells, P->n_dim, P->option, P->dt, {}};
+    for (int n = 1; n <= kMaxSpecies; ++n) B.k_max_n[n] = P->k_n[n];
+    for (int n = 1; n <= kMaxSpecies && rc == DRAG_OK; ++n) {
+      const bool lane = n <= P->lmax;
+      if ((lane ? V.n_lane[n] : V.n_wave_n[n]) == 0) continue;
+      BatchArgs X = B;
+      X.items = lane ? V.d_lane[n] : V.d_wave_n[n];
+      X.n_items = lane ? V.n_lane[n] : V.n_wave_n[n];
+      float kbest_ms = 0.0f;
+      int kbest = P->k_n[n];
+      for (int K = kTuneKMin; K <= 9 && rc == DRAG_OK; ++K) {
+        X.k_max_n[n] = K;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 3 && rc == DRAG_OK; ++rep) {  // rep 0 warms up
+          rc = hip_status(hipEventRecord(e0, st));
+          if (!rc) {
+            if (lane) batched_lane(n, X, st);
+            else batched_wave_n(n, X, gpb, st);
+            rc = hip_status(hipGetLastError());
+          }
+          if (!rc) rc = hip_status(hipEventRecord(e1, st));
+          if (!rc) rc = hip_status(hipEventSynchronize(e1));
+          float t = 0.0f;
+          if (!rc) rc = hip_status(hipEventElapsedTime(&t, e0, e1));
+          if (rep == 1 || (rep > 1 && t < ms)) ms = t;
+        }
+        if (!rc && (K == kTuneKMin || ms < kbest_ms)) {
+          kbest_ms = ms;
+          kbest = K;
+        }
+      }
+      if (!rc) P->k_n[n] = kbest;
+    }
+    // leave v_out holding the result of the chosen configuration
+    if (!rc) rc = plan_enqueue(P, P->lmax, P->wave_mode, fields, v_in, v_out, st, P->side_stream);
+    if (!rc) rc = hip_status(hipStreamSynchronize(st));
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   plan_drop_graph(P);
   if (rc) return rc;
-  P->lmax = best;
-  P->wave_mode = best_mode;
-  if (lane_max_out) *lane_max_out = best;
+  if (lane_max_out) *lane_max_out = P->lmax;
+  return DRAG_OK;
+}
+
+int drag_plan_k_max(const drag_plan* P, int32_t* k_max) {
+  if (!P) return DRAG_ERR_PLAN;
+  if (!k_max) return DRAG_ERR_NULL_POINTER;
+  for (int n = 1; n <= kMaxSpecies; ++n) k_max[n - 1] = P->k_n[n];
   return DRAG_OK;
 }
 
@@ -861,7 +943,7 @@ const char* drag_status_string(int code) {
     case DRAG_ERR_STEPS: return "n_steps < 0, or the history would overflow 64-bit offsets";
     case DRAG_ERR_LD: return "ld < n_cells or ld too large";
     case DRAG_ERR_DT: return "dt is NaN, infinite or negative";
-    case DRAG_ERR_K_MAX: return "k_max outside [1, 9]";
+    case DRAG_ERR_K_MAX: return "k_max outside [0 (auto), 9]";
     case DRAG_ERR_OPTION: return "option not 0, 1 or 2";
     case DRAG_ERR_NULL_POINTER: return "a required pointer is NULL";
     case DRAG_ERR_ALIAS: return "an output overlaps an input";
@@ -889,6 +971,20 @@ int drag_select(double norm, int32_t k_max, int32_t option, int32_t* k, int32_t*
   if (k) *k = r.k;
   if (m) *m = r.m;
   if (s) *s = r.s;
+  return DRAG_OK;
+}
+
+int drag_set_k_max(int32_t n_species, int32_t k_max) {
+  if (n_species < 1 || n_species > kMaxSpecies) return DRAG_ERR_N_SPECIES;
+  if (k_max < DRAG_K_AUTO || k_max > 9) return DRAG_ERR_K_MAX;
+  g_kmax_override[n_species - 1] = k_max;
+  return DRAG_OK;
+}
+
+int drag_get_k_max(int32_t n_species, int32_t* k_max) {
+  if (n_species < 1 || n_species > kMaxSpecies) return DRAG_ERR_N_SPECIES;
+  if (!k_max) return DRAG_ERR_NULL_POINTER;
+  *k_max = k_for(DRAG_K_AUTO, n_species);
   return DRAG_OK;
 }
 

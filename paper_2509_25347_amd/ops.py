@@ -317,6 +317,12 @@ class BatchPlan:
         _lib.check(_lib.lib().drag_plan_set_config(self._plan, int(lane_max), int(mfma_mode)),
                    "drag_plan_set_config")
 
+    def k_max(self):
+        """The Taylor cap K per species count, index N - 1 (drag_plan_k_max)."""
+        ks = (ctypes.c_int32 * 16)()
+        _lib.check(_lib.lib().drag_plan_k_max(self._plan, ks), "drag_plan_k_max")
+        return list(ks)
+
     def close(self):
         if getattr(self, "_plan", None) is not None and self._plan.value:
             _lib.lib().drag_plan_destroy(self._plan)

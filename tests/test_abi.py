@@ -71,7 +71,7 @@ def test_argument_errors_return_before_launch(L):
     assert _apply(L, mk(dt=-1.0), base) == _lib.ERR_DT
     assert _apply(L, mk(dt=float("nan")), base) == _lib.ERR_DT
     assert _apply(L, mk(dt=float("inf")), base) == _lib.ERR_DT
-    assert _apply(L, mk(k_max=0), base) == _lib.ERR_K_MAX
+    assert _apply(L, mk(k_max=-1), base) == _lib.ERR_K_MAX
     assert _apply(L, mk(k_max=10), base) == _lib.ERR_K_MAX
     assert _apply(L, mk(option=3), base) == _lib.ERR_OPTION
     assert _apply(L, mk(), [1 << 20, 0, 3 << 20, 4 << 20, 8 << 20]) == _lib.ERR_NULL_POINTER
@@ -123,7 +123,7 @@ def test_batched_plan_argument_errors(L):
     assert L.drag_plan_batched(ctypes.byref(d(n_blocks=0)), ctypes.byref(plan)) == _lib.ERR_PLAN
     assert L.drag_plan_batched(ctypes.byref(d(n_dim=4)), ctypes.byref(plan)) == _lib.ERR_N_DIM
     assert L.drag_plan_batched(ctypes.byref(d(dt=-1.0)), ctypes.byref(plan)) == _lib.ERR_DT
-    assert L.drag_plan_batched(ctypes.byref(d(k_max=0)), ctypes.byref(plan)) == _lib.ERR_K_MAX
+    assert L.drag_plan_batched(ctypes.byref(d(k_max=-1)), ctypes.byref(plan)) == _lib.ERR_K_MAX
     assert L.drag_plan_batched(ctypes.byref(d(option=5)), ctypes.byref(plan)) == _lib.ERR_OPTION
     bad = (ctypes.c_int32 * 3)(1, 0, 16)
     dd = d()
@@ -146,6 +146,25 @@ def test_mapping_controls(L):
         _lib.set_mapping(12, _lib.MAP_LANE)
     with pytest.raises(_lib.DragError):
         _lib.set_mapping(0, _lib.MAP_WAVE)
+
+
+def test_taylor_cap_controls(L):
+    """K_AUTO resolves per N to a cap in 3..9; overrides stick until reset;
+    out-of-range arguments are rejected without changing anything."""
+    ks = [_lib.get_k_max(N) for N in range(1, 17)]
+    assert all(3 <= k <= 9 for k in ks)
+    _lib.set_k_max(5, 8)
+    assert _lib.get_k_max(5) == 8
+    _lib.set_k_max(5, _lib.K_AUTO)
+    assert _lib.get_k_max(5) == ks[4]
+    for bad in ((0, 5), (17, 5), (5, 10), (5, -1)):
+        with pytest.raises(_lib.DragError):
+            _lib.set_k_max(*bad)
+    assert [_lib.get_k_max(N) for N in range(1, 17)] == ks
+    k = ctypes.c_int32()
+    assert L.drag_get_k_max(5, None) == _lib.ERR_NULL_POINTER
+    assert L.drag_get_k_max(0, ctypes.byref(k)) == _lib.ERR_N_SPECIES
+    assert L.drag_plan_k_max(None, ctypes.byref(k)) == _lib.ERR_PLAN
 
 
 def test_expm_steps_argument_errors(L):

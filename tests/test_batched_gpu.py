@@ -30,8 +30,9 @@ def ops(dev):
     return _ops
 
 
-def plain_per_block(ops, batch, dev, lane_max):
-    """drag_expm_apply on every block with the batched plan's mapping."""
+def plain_per_block(ops, batch, dev, lane_max, k_max=None):
+    """drag_expm_apply on every block with the batched plan's mapping (and
+    Taylor cap k_max[N - 1] when given, else K = 9)."""
     from paper_2509_25347_amd import _lib
     outs = []
     try:
@@ -40,8 +41,9 @@ def plain_per_block(ops, batch, dev, lane_max):
         for blk in batch["blocks"]:
             T = {k: torch.from_numpy(np.ascontiguousarray(blk[k])).to(dev)
                  for k in ("rho_g", "rho_d", "t_stop", "v")}
+            K = 9 if k_max is None else k_max[blk["rho_d"].shape[0] - 1]
             outs.append(ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
-                                       batch["dt"]).cpu().numpy())
+                                       batch["dt"], k_max=K).cpu().numpy())
     finally:
         for N in range(1, 17):
             _lib.set_mapping(N, _lib.MAP_AUTO)
@@ -92,6 +94,38 @@ def test_autotune_and_every_variant_result(ops, dev):
             torch.cuda.synchronize()
             for b in range(len(batch["blocks"])):
                 assert np.array_equal(plan.block_view(o, b).cpu().numpy(), refs[lmax][b]), (lmax, mode, b)
+    plan.close()
+
+
+def test_auto_taylor_cap_plan(ops, dev, orc):
+    """A K_AUTO plan starts from the library's per-N caps, the autotuner picks
+    a cap per N in 3..9, and every block is then bit-identical to the plain
+    launch with that cap (and within the oracle's bar for it); v_out of the
+    autotune call already holds that result."""
+    from paper_2509_25347_amd import _lib
+    batch = W.make_batched(n_blocks=64, block_cells=96, seed_cfg=47)
+    plan = ops.BatchPlan(batch["n_species"], 96, 3, batch["dt"], k_max=_lib.K_AUTO)
+    assert plan.k_max() == [_lib.get_k_max(N) for N in range(1, 17)]
+    fields, v = plan.pack(batch["blocks"], dev)
+    out = torch.empty_like(v)
+    lm = plan.autotune(fields, v, out)
+    torch.cuda.synchronize()
+    ks = plan.k_max()
+    assert all(3 <= k <= 9 for k in ks)
+    out2 = plan.apply(fields, v)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    ref = plain_per_block(ops, batch, dev, lane_max=lm, k_max=ks)
+    for b, blk in enumerate(batch["blocks"]):
+        got = plan.block_view(out2, b).cpu().numpy()
+        assert np.array_equal(got, ref[b]), b
+        if b % 8 == 0:
+            K = ks[blk["rho_d"].shape[0] - 1]
+            o, kms, nrm, st = orc.apply_cells(blk["rho_g"], blk["rho_d"], blk["t_stop"], blk["v"],
+                                              batch["dt"], K=K)
+            scale = np.abs(blk["v"]).max(axis=1)
+            e = (np.abs(got - o).max(axis=1) / scale).max(axis=0)
+            assert (e <= np.maximum(4 * U * nrm, 1e-13)).all(), (b, K)
     plan.close()
 
 

@@ -180,6 +180,30 @@ def test_full_size_stiff_n16_sampled(ops, dev, orc):
     assert et.max() <= 1e-13, et.max()
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 16])
+def test_auto_taylor_cap(ops, dev, orc, N):
+    """k_max = K_AUTO runs the library's per-N cap: the same bits as asking
+    for that K, within the oracle's bar for that K and the exact
+    exponential's 1e-13; the adjoint resolves the same K."""
+    from paper_2509_25347_amd import _lib
+    K = _lib.get_k_max(N)
+    d = W.make_stiff(N, 333)
+    T = _to(d, dev)
+    a = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"], k_max=_lib.K_AUTO)
+    b = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"], k_max=K)
+    assert torch.equal(a, b)
+    ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"], K=K)
+    assert_parity(a.cpu().numpy(), ref, nrm, d, f"N={N} K={K}")
+    et = cell_errors(a.cpu().numpy(), truth_apply(d), d["v"])
+    assert np.nanmax(et) <= 1e-13
+    w = torch.randn_like(T["v"])
+    ga = ops.expm_apply_backward(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], w, d["dt"],
+                                 k_max=_lib.K_AUTO)
+    gb = ops.expm_apply_backward(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], w, d["dt"], k_max=K)
+    for x, y in zip(ga, gb):
+        assert torch.equal(x, y)
+
+
 def test_dt_zero_identity_and_in_place(ops, dev):
     for name in ("n4_3d", "n16_stiff_3d"):
         d = W.make(name, 1000)
