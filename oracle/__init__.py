@@ -75,6 +75,8 @@ def _load():
     lib.orc_grad_cells.argtypes = [i64, i, i, i64, d, i, i, vp, vp, vp, vp, vp,
                                    vp, vp, vp, vp, vp]
     lib.orc_grad_cells.restype = i
+    lib.orc_taylor_stage.argtypes = [i, vp, i, i, vp, P(i), P(d)]
+    lib.orc_taylor_stage.restype = i
     lib.orc_rk1_cells.argtypes = [i64, i, i, i64, d, vp, vp, vp, vp, vp]
     lib.orc_rk1_cells.restype = i
     lib.truth_expm_eigen.argtypes = [i, d, d, vp, vp, vp]
@@ -164,6 +166,24 @@ def cell_expm(dt, rho_g, rho_d, t_stop, K=9, option=2, xform=False):
     if bad:
         raise ValueError("bad cell (bits %d)" % bad)
     return E, tuple(int(x) for x in kms)
+
+
+BOUND_TEST = 4  # option bit: Sastre's second modification in the Taylor stage
+
+
+def taylor_stage(B, k, bound_test=False):
+    """F = T_m(B) - I for row k of Table B.1 on the given (scaled) matrix B,
+    with or without the bound test; returns (F, products skipped, b_exp)."""
+    lib = _load()
+    B = _f64(B)
+    n = B.shape[0]
+    F = np.zeros((n, n))
+    sk = ctypes.c_int()
+    be = ctypes.c_double()
+    if lib.orc_taylor_stage(n, _ptr(B), int(k), int(bool(bound_test)), _ptr(F),
+                            ctypes.byref(sk), ctypes.byref(be)) != 0:
+        raise ValueError("bad Taylor-stage arguments")
+    return F, sk.value, be.value
 
 
 def grad_A(A, nrm, G, K=9, option=2):

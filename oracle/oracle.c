@@ -248,20 +248,76 @@ typedef struct {
     double U[ORC_NMAX * ORC_NMAX];
 } work_t;
 
+/* 1-norm (largest column sum of absolute values) of an n x n matrix. */
+static double norm1(int n, const double *X)
+{
+    double best = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += fabs(X[i * n + j]);
+        if (s > best) best = s;
+    }
+    return best;
+}
+
+/* b_exp of the second modification (Appendix B, eq. Pat_Stk6 and the
+ * "compute bound" algorithm): an estimate of ||e^-B|| from the blocks of
+ * T_m(-B),
+ *     b_exp = ||b0 I + Bhat_0|| + sum_{l=1}^{r-1} ||Bhat_l|| ||B^q||^l,
+ *     Bhat_l = sum_{j=1}^{q} (-1)^(ql+j) b_{ql+j} B^j,
+ * accumulated from l = r-1 down (Horner in ||B^q||).  Reading: the index of
+ * Bhat inside the loop is l (the printed listings write r-1 in one version
+ * and k in the other). */
+static double bound_bexp(int n, int q, int r, work_t *w)
+{
+    const int nn = n * n;
+    const double nq = norm1(n, w->P[q]);
+    double b = 0.0;
+    for (int l = r - 1; l >= 0; --l) {
+        memset(w->Bbar, 0, sizeof(double) * nn);
+        for (int j = 1; j <= q; ++j) {
+            const int i = q * l + j;
+            const double c = (i % 2 ? -1.0 : 1.0) * TAYLOR_B[i];
+            for (int t = 0; t < nn; ++t) w->Bbar[t] += c * w->P[j][t];
+        }
+        if (l >= 1) {
+            b = (norm1(n, w->Bbar) + b) * nq;
+        } else {
+            for (int i = 0; i < n; ++i) w->Bbar[i * n + i] += TAYLOR_B[0];
+            b = b + norm1(n, w->Bbar);
+        }
+    }
+    return b;
+}
+
 /* Taylor stage of the merged Paterson-Stockmeyer / Horner evaluation
- * (Appendix B, "New Taylor polynomial evaluation without bound-test"):
+ * (Appendix B, "New Taylor polynomial evaluation", eqs. Pat_Stk-Pat_Stk3):
  *   T_m(B) = b0 I + sum_{k=0}^{r-1} Bbar_k (B^q)^k,
  *   Bbar_k = sum_{j=1}^{q} b_{qk+j} B^j.
  * The identity term is left out, so F = T_m(B) - I.  The paper recomputes
  * the powers B^j inside the k loop to avoid storing them; they are the same
- * products in the same order, so they are computed once here. */
+ * products in the same order, so they are computed once here.
+ *
+ * bound_test != 0 adds Sastre's second modification (eqs. Pat_Stk4-Pat_stk7
+ * and the evaluation with the bound test): before the product that carries
+ * the accumulated higher blocks T = Bbar_k + F to level k, the part
+ * T (B^q)^k is dropped when b_exp ||T|| ||B^q||^k <= u (u = 2^-53): since
+ * ||e^B||^-1 <= ||e^-B|| ~ b_exp, it is then below u relative to ||e^B||.
+ * *skipped counts the products saved (NULL: not reported). */
 static void taylor_minus_identity(int n, const double *B, int q, int r,
-                                  work_t *w, double *F)
+                                  work_t *w, double *F, int bound_test,
+                                  int *skipped)
 {
     const int nn = n * n;
     memcpy(w->P[1], B, sizeof(double) * nn);
     for (int j = 2; j <= q; ++j) mat_mul(n, B, w->P[j - 1], w->P[j]);
 
+    double bexp = 0.0, nq = 0.0;
+    if (bound_test) {
+        bexp = bound_bexp(n, q, r, w);
+        nq = norm1(n, w->P[q]);
+    }
+    int skips = 0;
     memset(F, 0, sizeof(double) * nn);
     for (int k = r - 1; k >= 0; --k) {
         memset(w->Bbar, 0, sizeof(double) * nn);
@@ -270,17 +326,49 @@ static void taylor_minus_identity(int n, const double *B, int q, int r,
             for (int t = 0; t < nn; ++t) w->Bbar[t] += b * w->P[j][t];
         }
         for (int t = 0; t < nn; ++t) w->T[t] = w->Bbar[t] + F[t];
-        if (k >= 1)
-            mat_mul(n, w->T, w->P[q], F);     /* F = (Bbar_k + F) B^q */
-        else
+        if (k >= 1) {
+            int drop = 0;
+            if (bound_test) {
+                double pk = 1.0;
+                for (int i = 0; i < k; ++i) pk *= nq;
+                drop = bexp * norm1(n, w->T) * pk <= ldexp(1.0, -53);
+            }
+            if (drop) {
+                memset(F, 0, sizeof(double) * nn);   /* T (B^q)^k neglected */
+                ++skips;
+            } else {
+                mat_mul(n, w->T, w->P[q], F);       /* F = (Bbar_k + F) B^q */
+            }
+        } else {
             memcpy(F, w->T, sizeof(double) * nn);
+        }
     }
+    if (skipped) *skipped = skips;
 }
 
+/* The Taylor stage alone on a given (already scaled) n x n matrix B:
+ * F = T_m(B) - I for row k of Table B.1, with or without the bound test;
+ * *skipped = products saved, *bexp_out = b_exp (either may be NULL). */
+int orc_taylor_stage(int n, const double *B, int k, int bound_test, double *F,
+                     int *skipped, double *bexp_out)
+{
+    if (n < 1 || n > ORC_NMAX || k < 1 || k > 9) return -1;
+    work_t *w = (work_t *)malloc(sizeof(work_t));
+    if (!w) return -2;
+    taylor_minus_identity(n, B, TB_Q[k], TB_R[k], w, F, bound_test, skipped);
+    if (bexp_out) *bexp_out = bound_bexp(n, TB_Q[k], TB_R[k], w);
+    free(w);
+    return 0;
+}
+
+/* option: Alg. 1 option (0, 1, 2), ORed with ORC_BOUND_TEST for the second
+ * modification in the Taylor stage. */
 static void expm_ws(int n, const double *A, double nrm, int K, int option,
                     int xform, double *Y, int *kms, work_t *w)
 {
     const int nn = n * n;
+    const int bound_test = option & ORC_BOUND_TEST;
+    option &= 3;
     int k, m, s;
     orc_select(nrm, K, option, &k, &m, &s);
     kms[0] = k; kms[1] = m; kms[2] = s;
@@ -288,7 +376,7 @@ static void expm_ws(int n, const double *A, double nrm, int K, int option,
     double *B = w->U;
     for (int t = 0; t < nn; ++t) B[t] = ldexp(A[t], -s);     /* 2^-s A */
 
-    taylor_minus_identity(n, B, TB_Q[k], TB_R[k], w, Y);
+    taylor_minus_identity(n, B, TB_Q[k], TB_R[k], w, Y, bound_test, NULL);
 
     if (!xform) {
         /* Y-form squaring: (I+Y)^2 = I + 2Y + Y Y */
@@ -311,7 +399,9 @@ int orc_expm(int N, const double *A, double nrm, int K, int option, int xform,
              double *Y, int *kms)
 {
     const int n = N + 1;
-    if (n > ORC_NMAX || K < 1 || K > 9 || option < 0 || option > 2) return -1;
+    if (n > ORC_NMAX || K < 1 || K > 9 || (option & ~ORC_BOUND_TEST) < 0 ||
+        (option & ~ORC_BOUND_TEST) > 2)
+        return -1;
     if (!isfinite(nrm)) return -1;
     work_t *w = (work_t *)malloc(sizeof(work_t));
     if (!w) return -2;
@@ -334,7 +424,8 @@ int orc_apply_cells(int64_t C, int N, int D, int64_t ld, double dt, int K,
 {
     const int n = N + 1, nn = n * n;
     if (n > ORC_NMAX || D < 1 || D > 3 || ld < C) return -1;
-    if (K < 1 || K > 9 || option < 0 || option > 2) return -1;
+    if (K < 1 || K > 9 || (option & ~ORC_BOUND_TEST) < 0 || (option & ~ORC_BOUND_TEST) > 2)
+        return -1;
     double *A = (double *)malloc(sizeof(double) * nn);
     double *Y = (double *)malloc(sizeof(double) * nn);
     work_t *w = (work_t *)malloc(sizeof(work_t));
@@ -407,7 +498,8 @@ int orc_grad_A(int N, const double *A, double nrm, int K, int option,
                const double *G, double *Abar, int *kms)
 {
     const int n = N + 1, nn = n * n;
-    if (n > ORC_NMAX || !isfinite(nrm)) return -1;
+    /* the gradient is of the evaluation without the bound test */
+    if (n > ORC_NMAX || !isfinite(nrm) || option < 0 || option > 2) return -1;
     int k, m, s;
     orc_select(nrm, K, option, &k, &m, &s);
     kms[0] = k; kms[1] = m; kms[2] = s;
