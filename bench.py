@@ -255,6 +255,7 @@ def main():
         res["fwd_bwd_vs_fwd"] = adjoint_measurement(torch, ops, workloads, dev)
         res["batched_vs_plain"] = batched_measurement(torch, ops, workloads, dev)
         res["rk1_vs_expm"] = rk1_measurement(torch, ops, workloads, dev)
+        res["bound_test"] = bound_test_measurement(torch, ops, _lib, workloads, dev)
     if args.extra:
         res["extra"] = extra_measurements(torch, ops, workloads, dev)
     if not args.no_cpu_baseline:
@@ -464,6 +465,32 @@ def rk1_measurement(torch, ops, workloads, dev, names=("n16_stiff_3d", "n8_adjoi
                      "expm_over_rk1": t_exp / t_rk1, "rk1_cells_per_s": C / (t_rk1 * 1e-3),
                      "rk1_roofline": rk1_roofline(t_rk1, C, N, D, name),
                      "rk1_step_gap_to_exp": {"median": float(gap.median()), "max": float(gap.max())}}
+    return res
+
+
+def bound_test_measurement(torch, ops, _lib, workloads, dev):
+    """Sastre's second modification (option bit DRAG_OPTION_BOUND_TEST, MFMA
+    kernel) against the same MFMA kernel without it: time, and the cells
+    whose result it changed (where a product was dropped and the rounding
+    differs)."""
+    res = {}
+    for name in ("n16_stiff_3d", "n8_adjoint_3d", "n1_closed_form"):
+        d = workloads.make(name)
+        N = d["rho_d"].shape[0]
+        T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
+        o1, o2 = torch.empty_like(T["v"]), torch.empty_like(T["v"])
+        try:
+            _lib.set_mapping(N, _lib.MAP_WAVE)
+            t0 = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                     d["dt"], out=o1), 20, 3)
+        finally:
+            _lib.set_mapping(N, _lib.MAP_AUTO)
+        t1 = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                 d["dt"], option=2 | _lib.OPTION_BOUND_TEST,
+                                                 out=o2), 20, 3)
+        changed = int(((o1 - o2).abs().amax(dim=(0, 1)) > 0).sum())
+        res[name] = {"mfma_ms": t0, "mfma_bound_test_ms": t1, "time_ratio": t1 / t0,
+                     "cells_changed": changed, "n_cells": int(d["rho_g"].shape[0])}
     return res
 
 

@@ -59,7 +59,8 @@ extern "C" {
 #define DRAG_ERR_LD            -5  /* ld < n_cells, or ld too large for 64-bit offsets */
 #define DRAG_ERR_DT            -6  /* dt NaN, infinite or < 0 */
 #define DRAG_ERR_K_MAX         -7  /* k_max outside [0, 9] */
-#define DRAG_ERR_OPTION        -8  /* option not 0, 1 or 2 */
+#define DRAG_ERR_OPTION        -8  /* option not 0, 1 or 2 (| DRAG_OPTION_BOUND_TEST
+                                      where accepted) */
 #define DRAG_ERR_NULL_POINTER  -9  /* a required array pointer is NULL (n_cells > 0) */
 #define DRAG_ERR_ALIAS        -10  /* an output overlaps an input it may not alias */
 #define DRAG_ERR_PLAN         -11  /* invalid batched plan or block table */
@@ -87,8 +88,23 @@ typedef struct drag_desc {
     int32_t k_max;     /* K of Alg. 1, 1..9 (9: m up to 30, Table B.1), or
                           DRAG_K_AUTO: the library's tuned K for n_species
                           (drag_get_k_max) */
-    int32_t option;    /* Alg. 1 option: 0 standard, 1, 2 (fewest products) */
+    int32_t option;    /* Alg. 1 option: 0 standard, 1, 2 (fewest products),
+                          optionally ORed with DRAG_OPTION_BOUND_TEST */
 } drag_desc;
+
+/*
+ * option bit: Sastre's second modification in the Taylor stage (Appendix B,
+ * eqs. Pat_Stk4-Pat_Stk7, the bound b_exp of eq. Pat_Stk6 and the
+ * evaluation with the bound test): a Horner product of the Paterson-
+ * Stockmeyer evaluation is skipped when the accumulated higher-degree part
+ * it would carry is below u relative to the estimate b_exp of ||e^-A||.
+ * drag_expm_apply and drag_expm_steps then run the MFMA kernel for every N
+ * (the test works on the kernel's own Paterson-Stockmeyer blocks of the
+ * reduced N x N matrix); drag_build ignores the bit; the adjoint and the
+ * batched plan reject it (DRAG_ERR_OPTION).  Results stay u-accurate; the
+ * products saved are data-dependent (none on the stiff N = 16 workload).
+ */
+#define DRAG_OPTION_BOUND_TEST 4
 
 /* Fill `d` with the defaults: k_max = 9, option = 2, ld = n_cells. */
 void drag_desc_init(drag_desc *d, int64_t n_cells, int32_t n_species,

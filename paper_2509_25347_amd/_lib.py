@@ -51,6 +51,7 @@ CELL_BAD_NORM = 8
 
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 K_AUTO = 0
+OPTION_BOUND_TEST = 4  # option bit: the second modification (bound test)
 
 EXPORTS = [
     "drag_desc_init", "drag_build", "drag_expm_apply", "drag_expm_steps", "drag_rk1_apply", "drag_expm_apply_backward",

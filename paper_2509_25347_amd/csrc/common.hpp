@@ -133,7 +133,7 @@ struct CellArgs {
   double dt;
   int n_dim;
   int k_max;
-  int option;
+  int option;  // Alg. 1 option, 0..2
 };
 
 struct BackArgs {

@@ -106,10 +106,11 @@ static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
   return hip_status(hipGetLastError());
 }
 
-template <int N>
+template <int N, bool BT = false>
 static int launch_forward_wave(const CellArgs& A, hipStream_t st) {
   const Grid gr = grid_for((A.n_cells + 15) / 16);  // a quad of cells per wavefront
-  hipLaunchKernelGGL(k_forward_wave<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  hipLaunchKernelGGL((k_forward_wave<N, BT>), dim3(gr.blocks), dim3(256), 0, st, A,
+                     gr.xcd_blocks);
   return hip_status(hipGetLastError());
 }
 
@@ -192,6 +193,19 @@ static FwdFn rk1_fwd(int N) {
   return tab[N - 1];
 }
 
+// The forward with Sastre's second modification in the Taylor stage (the
+// bound test): MFMA kernel for every N.
+static FwdFn wave_fwd_bound_test(int N) {
+  static const FwdFn tab[16] = {
+      launch_forward_wave<1, true>,  launch_forward_wave<2, true>,  launch_forward_wave<3, true>,
+      launch_forward_wave<4, true>,  launch_forward_wave<5, true>,  launch_forward_wave<6, true>,
+      launch_forward_wave<7, true>,  launch_forward_wave<8, true>,  launch_forward_wave<9, true>,
+      launch_forward_wave<10, true>, launch_forward_wave<11, true>, launch_forward_wave<12, true>,
+      launch_forward_wave<13, true>, launch_forward_wave<14, true>, launch_forward_wave<15, true>,
+      launch_forward_wave<16, true>};
+  return tab[N - 1];
+}
+
 static FwdFn lane_fwd(int N) {
   static const FwdFn tab[kLaneMaxN] = {
       launch_forward_lane<1>, launch_forward_lane<2>, launch_forward_lane<3>,
@@ -264,7 +278,8 @@ static int check_desc(const drag_desc* d) {
   if (d->ld > (INT64_MAX / 64)) return DRAG_ERR_LD;
   if (!(d->dt >= 0.0) || !isfinite(d->dt)) return DRAG_ERR_DT;
   if (d->k_max < DRAG_K_AUTO || d->k_max > 9) return DRAG_ERR_K_MAX;
-  if (d->option < 0 || d->option > 2) return DRAG_ERR_OPTION;
+  const int opt = d->option & ~DRAG_OPTION_BOUND_TEST;
+  if (opt < 0 || opt > 2) return DRAG_ERR_OPTION;
   return DRAG_OK;
 }
 
@@ -621,7 +636,7 @@ int drag_build(const drag_desc* d, const double* rho_g, const double* rho_d,
     for (int y = x + 1; y < 6; ++y)
       if (overlap(out[x], out[y])) return DRAG_ERR_ALIAS;
   BuildArgs B{rho_g, rho_d, t_stop, a_out, e_out, norm_out, k_out, m_out, s_out,
-              C,     ld,    d->dt,  (int)N, k_for(d->k_max, (int)N), d->option};
+              C,     ld,    d->dt,  (int)N, k_for(d->k_max, (int)N), d->option & 3};
   const Grid gr = grid_for((C + 255) / 256);
   hipLaunchKernelGGL(k_build, dim3(gr.blocks), dim3(256), 0, (hipStream_t)stream, B,
                      gr.xcd_blocks);
@@ -643,7 +658,8 @@ int drag_expm_apply(const drag_desc* d, const double* rho_g, const double* rho_d
   if ((const double*)v_out != v_in && overlap(ro, span(v_in, D * (N + 1), ld, C)))
     return DRAG_ERR_ALIAS;
   CellArgs A{rho_g, rho_d, t_stop, v_in, v_out, C,
-             ld,    d->dt, (int)D, k_for(d->k_max, (int)N), d->option};
+             ld,    d->dt, (int)D, k_for(d->k_max, (int)N), d->option & 3};
+  if (d->option & DRAG_OPTION_BOUND_TEST) return wave_fwd_bound_test((int)N)(A, (hipStream_t)stream);
   const int map = mapping_for((int)N);
   return map == DRAG_MAP_LANE ? lane_fwd((int)N)(A, (hipStream_t)stream)
                               : wave_fwd((int)N)(A, (hipStream_t)stream);
@@ -663,7 +679,7 @@ int drag_rk1_apply(const drag_desc* d, const double* rho_g, const double* rho_d,
     return DRAG_ERR_ALIAS;
   if ((const double*)v_out != v_in && overlap(ro, span(v_in, D * (N + 1), ld, C)))
     return DRAG_ERR_ALIAS;
-  CellArgs A{rho_g, rho_d, t_stop, v_in, v_out, C, ld, d->dt, (int)D, d->k_max, d->option};
+  CellArgs A{rho_g, rho_d, t_stop, v_in, v_out, C, ld, d->dt, (int)D, d->k_max, d->option & 3};
   return rk1_fwd((int)N)(A, (hipStream_t)stream);
 }
 
@@ -731,6 +747,8 @@ int drag_expm_apply_backward(const drag_desc* d, const double* rho_g, const doub
     for (int y = x + 1; y < 6; ++y)
       if (overlap(out[x], out[y])) return DRAG_ERR_ALIAS;
   }
+  // the adjoint differentiates the evaluation without the bound test
+  if (d->option & DRAG_OPTION_BOUND_TEST) return DRAG_ERR_OPTION;
   BackArgs B{rho_g, rho_d, t_stop, v_in, w, v_out, g_v, g_logt, g_t, g_rho_d, g_rho_g,
              C,     ld,    d->dt,  (int)D, k_for(d->k_max, (int)N), d->option};
   const int map = mapping_for_bwd((int)N);
@@ -944,7 +962,7 @@ const char* drag_status_string(int code) {
     case DRAG_ERR_LD: return "ld < n_cells or ld too large";
     case DRAG_ERR_DT: return "dt is NaN, infinite or negative";
     case DRAG_ERR_K_MAX: return "k_max outside [0 (auto), 9]";
-    case DRAG_ERR_OPTION: return "option not 0, 1 or 2";
+    case DRAG_ERR_OPTION: return "option not 0, 1 or 2, or a bound-test bit this call does not take";
     case DRAG_ERR_NULL_POINTER: return "a required pointer is NULL";
     case DRAG_ERR_ALIAS: return "an output overlaps an input";
     case DRAG_ERR_PLAN: return "invalid batched plan or block table";

@@ -182,7 +182,16 @@ constexpr int kPsR[10] = {0, 1, 1, 2, 2, 3, 4, 4, 5, 6};
 // P_jj = M^jj in the structured form, Bbar_k = sum_{jj=1}^{Q} b_{Qk+jj} P_jj,
 // then Horner F = Bbar_{r-1}; F = Bbar_k + F P_Q, k = r-2..0 on the matrix
 // cores (P_Q is the B operand straight from registers).
-template <int Q>
+// ||X||_1 of a tile in the D layout (largest column sum of |X|), the same in
+// every lane: the four row pieces of column j summed over the lane rows, then
+// the largest over the 16 columns.  Additions are paired the same way in
+// every lane and max is exact, so the value is bit-identical across lanes.
+__device__ __forceinline__ double norm1_tile(const v4d& X) {
+  const double part = (fabs(X[0]) + fabs(X[1])) + (fabs(X[2]) + fabs(X[3]));
+  return row_max(sum_rows(part));
+}
+
+template <int Q, bool BT = false>
 __device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const double (&rm)[4],
                                          int m, int r, double* stage, int g, int j) {
   v4d P[Q + 1];
@@ -203,13 +212,58 @@ __device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const 
     return acc;
   };
   v4d F = bbar(r - 1);
+  if constexpr (!BT) {
+    for (int k = r - 2; k >= 0; --k) {
+      double Af[4];
+      stage_tile(stage, g, j, F);
+      load_a_ops(stage, g, j, Af);
+      F = mma16(Af, Bq, bbar(k));
+    }
+    return F;
+  } else {
+  // Second modification (Appendix B, eqs. Pat_Stk4-Pat_Stk6) on this split:
+  // b_exp = ||I + Bhat_0|| + sum_{l>=1} ||Bhat_l|| ||M^Q||^l estimates
+  // ||e^-M|| from the blocks of T_m(-M); before the product that carries the
+  // accumulated F to level k, F (M^Q)^(k+1) is dropped when
+  // b_exp ||F|| ||M^Q||^(k+1) <= u, i.e. when it is below u relative to
+  // ||e^M||.  The decisions are wave-uniform (the norms are the same bits in
+  // every lane), so a dropped product is not issued.
+  auto bhat = [&](int l) {
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int jj = 1; jj <= Q; ++jj) {
+      const int i = Q * l + jj;
+      const double cf = (i <= m) ? ((i & 1) ? -kInvFact[i] : kInvFact[i]) : 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = fma(cf, P[jj][v], acc[v]);
+    }
+    return acc;
+  };
+  const double nq = norm1_tile(P[Q]);
+  double bexp = 0.0;
+  for (int l = r - 1; l >= 1; --l) bexp = (norm1_tile(bhat(l)) + bexp) * nq;
+  {
+    v4d H = bhat(0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (4 * v + g == j) H[v] += rm[v];  // the identity of the N x N block
+    bexp = bexp + norm1_tile(H);
+  }
   for (int k = r - 2; k >= 0; --k) {
-    double Af[4];
-    stage_tile(stage, g, j, F);
-    load_a_ops(stage, g, j, Af);
-    F = mma16(Af, Bq, bbar(k));
+    double pk = 1.0;  // ||M^Q||^(k+1)
+    for (int i = 0; i <= k; ++i) pk *= nq;
+    const bool neg = bexp * norm1_tile(F) * pk <= 0x1p-53;
+    if (__builtin_amdgcn_readfirstlane((int)neg)) {
+      F = bbar(k);
+    } else {
+      double Af[4];
+      stage_tile(stage, g, j, F);
+      load_a_ops(stage, g, j, Af);
+      F = mma16(Af, Bq, bbar(k));
+    }
   }
   return F;
+  }
 }
 
 // One squaring of the Y form, Z <- 2 Z + Z Z, issued as (Z + 2 I) Z: Z is
@@ -287,6 +341,8 @@ __device__ __forceinline__ QuadCell quad_setup(const double* rho_g, const double
 
 // With store = false the outputs stay in the quad's LDS block (vs) for the
 // workgroup to store (group_store).
+// BT: the Taylor stage with the second modification (bound test).
+template <bool BT = false>
 __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N, int64_t c0,
                                                   int lane, double* lds, bool store = true) {
   const int g = lane >> 4, j = lane & 15;
@@ -391,10 +447,10 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
     }
     v4d Z;
     switch (q) {  // uniform; one code path per power count
-      case 2: Z = quad_poly<2>(M, R, rm, m, r, stage, g, j); break;
-      case 3: Z = quad_poly<3>(M, R, rm, m, r, stage, g, j); break;
-      case 4: Z = quad_poly<4>(M, R, rm, m, r, stage, g, j); break;
-      default: Z = quad_poly<5>(M, R, rm, m, r, stage, g, j); break;
+      case 2: Z = quad_poly<2, BT>(M, R, rm, m, r, stage, g, j); break;
+      case 3: Z = quad_poly<3, BT>(M, R, rm, m, r, stage, g, j); break;
+      case 4: Z = quad_poly<4, BT>(M, R, rm, m, r, stage, g, j); break;
+      default: Z = quad_poly<5, BT>(M, R, rm, m, r, stage, g, j); break;
     }
 
     // squarings Z <- (Z + 2 I) Z, two per trip so that the result and
@@ -456,8 +512,8 @@ __device__ __forceinline__ void group_store(const CellArgs& A, const int N, int6
   }
 }
 
-template <int N>
-__global__ void __launch_bounds__(256, 5) k_forward_wave(CellArgs A, int xcd_blocks) {
+template <int N, bool BT = false>
+__global__ void __launch_bounds__(256, BT ? 4 : 5) k_forward_wave(CellArgs A, int xcd_blocks) {
   __shared__ double lds[4 * kQuadDoubles];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -466,7 +522,7 @@ __global__ void __launch_bounds__(256, 5) k_forward_wave(CellArgs A, int xcd_blo
   const int64_t g0 = logical * 16;  // the workgroup's first cell
   if (g0 >= A.n_cells) return;     // uniform over the workgroup
   const int64_t c0 = g0 + 4 * w;
-  if (c0 < A.n_cells) wave_forward_quad(A, N, c0, lane, lds + w * kQuadDoubles, false);
+  if (c0 < A.n_cells) wave_forward_quad<BT>(A, N, c0, lane, lds + w * kQuadDoubles, false);
   __syncthreads();
   group_store(A, N, g0, lds);
 }

@@ -74,6 +74,8 @@ def test_argument_errors_return_before_launch(L):
     assert _apply(L, mk(k_max=-1), base) == _lib.ERR_K_MAX
     assert _apply(L, mk(k_max=10), base) == _lib.ERR_K_MAX
     assert _apply(L, mk(option=3), base) == _lib.ERR_OPTION
+    assert _apply(L, mk(option=3 | _lib.OPTION_BOUND_TEST), base) == _lib.ERR_OPTION
+    assert _apply(L, mk(option=8), base) == _lib.ERR_OPTION
     assert _apply(L, mk(), [1 << 20, 0, 3 << 20, 4 << 20, 8 << 20]) == _lib.ERR_NULL_POINTER
     # v_out overlapping rho_d (not the allowed in-place v_in)
     assert _apply(L, mk(), [1 << 20, 2 << 20, 3 << 20, 4 << 20, (2 << 20) + 8]) == _lib.ERR_ALIAS
@@ -89,6 +91,11 @@ def test_backward_argument_errors(L):
     bad = _lib.make_desc(10, 20, 3, 10, 1.0)
     assert L.drag_expm_apply_backward(ctypes.byref(bad), *nul) == _lib.ERR_N_SPECIES
     assert L.drag_expm_apply_backward(ctypes.byref(d), *nul) == _lib.ERR_NULL_POINTER
+    # the adjoint takes no bound test (checked before anything is enqueued)
+    bt = _lib.make_desc(10, 4, 3, 10, 1.0, 9, 2 | _lib.OPTION_BOUND_TEST)
+    ptrs = [ctypes.c_void_p(x) for x in (1 << 20, 2 << 20, 3 << 20, 4 << 20, 5 << 20)]
+    outs = [ctypes.c_void_p(x) for x in (6 << 20, 7 << 20, 8 << 20, 9 << 20, 10 << 20, 11 << 20)]
+    assert L.drag_expm_apply_backward(ctypes.byref(bt), *ptrs, *outs, None) == _lib.ERR_OPTION
 
 
 def test_table_matches_oracle(L, orc):

@@ -204,6 +204,41 @@ def test_auto_taylor_cap(ops, dev, orc, N):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("case", ["n1_closed_form", "n8_jittered", "n4_3d", "n12_stiff",
+                                  "n16_stiff_3d"])
+def test_bound_test_option(ops, dev, orc, case):
+    """option | OPTION_BOUND_TEST (the second modification, on the MFMA
+    kernel for every N): within the oracle's bar (the oracle running its own
+    bound test on the dense matrix) and the exact exponential's 1e-13, and
+    within 1e-13 of the MFMA kernel's result without it.  On the N = 1 cells
+    the test fires (some cells differ from that result), as it does in the
+    oracle (14 of 700 there)."""
+    from paper_2509_25347_amd import _lib
+    d = {"n8_jittered": lambda: W.make_jittered(8, 700), "n12_stiff": lambda: W.make_stiff(12, 700)
+         }.get(case, lambda: W.make(case, 700))()
+    T = _to(d, dev)
+    opt = 2 | _lib.OPTION_BOUND_TEST
+    got = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"], option=opt)
+    torch.cuda.synchronize()
+    ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"],
+                                        option=2 | orc.BOUND_TEST)
+    g = got.cpu().numpy()
+    assert_parity(g, ref, nrm, d, case)
+    et = cell_errors(g, truth_apply(d), d["v"])
+    assert np.nanmax(et) <= 1e-13
+    N = d["rho_d"].shape[0]
+    try:
+        _lib.set_mapping(N, _lib.MAP_WAVE)
+        plain = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"]).cpu().numpy()
+    finally:
+        _lib.set_mapping(N, _lib.MAP_AUTO)
+    assert cell_errors(g, plain, d["v"]).max() <= 1e-13
+    changed = int((np.abs(g - plain).max(axis=(0, 1)) > 0).sum())
+    print(f"bound test {case}: {changed} of {g.shape[-1]} cells changed")
+    if case == "n1_closed_form":
+        assert changed >= 1, case
+
+
 def test_dt_zero_identity_and_in_place(ops, dev):
     for name in ("n4_3d", "n16_stiff_3d"):
         d = W.make(name, 1000)
