@@ -75,6 +75,10 @@ def _load():
     lib.orc_grad_cells.argtypes = [i64, i, i, i64, d, i, i, vp, vp, vp, vp, vp,
                                    vp, vp, vp, vp, vp]
     lib.orc_grad_cells.restype = i
+    lib.orc_pade_row.argtypes = [i, P(i), P(d), vp]
+    lib.orc_pade_row.restype = i
+    lib.orc_pade_select.argtypes = [d, P(i), P(i)]
+    lib.orc_pade_select.restype = None
     lib.orc_taylor_stage.argtypes = [i, vp, i, i, vp, P(i), P(d)]
     lib.orc_taylor_stage.restype = i
     lib.orc_rk1_cells.argtypes = [i64, i, i, i64, d, vp, vp, vp, vp, vp]
@@ -169,6 +173,25 @@ def cell_expm(dt, rho_g, rho_d, t_stop, K=9, option=2, xform=False):
 
 
 BOUND_TEST = 4  # option bit: Sastre's second modification in the Taylor stage
+PADE = 8        # option bit: the diagonal Pade scaling step instead of Taylor
+
+
+def pade_row(i: int):
+    """(m, theta_m, coefficients c_0..c_m of N_mm) of the oracle's Pade row i = 0..4."""
+    lib = _load()
+    m, th = ctypes.c_int(), ctypes.c_double()
+    c = np.zeros(14)
+    if lib.orc_pade_row(i, ctypes.byref(m), ctypes.byref(th), _ptr(c)) != 0:
+        raise ValueError("row must be in 0..4")
+    return m.value, th.value, c[: m.value + 1].copy()
+
+
+def pade_select(nrm: float):
+    """(m, s) of the Pade scaling step for a finite norm."""
+    lib = _load()
+    m, s = ctypes.c_int(), ctypes.c_int()
+    lib.orc_pade_select(float(nrm), ctypes.byref(m), ctypes.byref(s))
+    return m.value, s.value
 
 
 def taylor_stage(B, k, bound_test=False):

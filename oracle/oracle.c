@@ -361,22 +361,140 @@ int orc_taylor_stage(int n, const double *B, int k, int bound_test, double *F,
     return 0;
 }
 
+/* ---- the diagonal Pade scaling step (Sect. 2.3, eq. PadeEqu, p = q = m) ---- */
+/* Degrees m and theta_m: the largest theta for which the backward error of
+ * the diagonal approximant r_m = N_mm / D_mm, log(e^-x r_m(x)) =
+ * sum_{k > 2m} c_k x^k, satisfies sum_k |c_k| theta^(k-1) <= u = 2^-53 (the
+ * criterion eq. B8 applies to the Taylor polynomial), computed in
+ * multiprecision from the power series.  The paper defines the approximant
+ * but gives no degree table; this one is the test's own. */
+static const int PADE_M[5] = {3, 5, 7, 9, 13};
+static const double PADE_THETA[5] = {
+    1.4955852179582915e-02,
+    2.539398330063232e-01,
+    9.504178996162932e-01,
+    2.0978479612570675e+00,
+    5.371920351148153e+00,
+};
+
+/* c_j = (2m - j)! m! / ((2m)! j! (m - j)!), j = 0..m: the coefficients of
+ * N_mm in eq. PadeEqu (those of D_mm are (-1)^j c_j), by the ratio of
+ * consecutive terms in binary128 and one rounding to double. */
+static void pade_coefs(int m, double *c)
+{
+    __float128 x = 1;
+    for (int j = 0; j <= m; ++j) {
+        c[j] = (double)x;
+        x = x * (__float128)(m - j) / ((__float128)(2 * m - j) * (__float128)(j + 1));
+    }
+}
+
+int orc_pade_row(int i, int *m, double *theta, double *coef)
+{
+    if (i < 0 || i > 4) return -1;
+    if (m) *m = PADE_M[i];
+    if (theta) *theta = PADE_THETA[i];
+    if (coef) pade_coefs(PADE_M[i], coef);
+    return 0;
+}
+
+/* (m, s) for a finite ||A||_1: the lowest degree whose theta covers ||A||
+ * (s = 0), else m = 13 and the smallest s with ||A|| <= theta_13 2^s
+ * (exact power-of-two comparisons). */
+void orc_pade_select(double nrm, int *mout, int *sout)
+{
+    for (int i = 0; i < 4; ++i) {
+        if (nrm <= PADE_THETA[i]) { *mout = PADE_M[i]; *sout = 0; return; }
+    }
+    int sh = 0;
+    while (nrm > ldexp(PADE_THETA[4], sh)) ++sh;
+    *mout = 13;
+    *sout = sh;
+}
+
+/* Z = r_m(B) - I.  With V and U the even and odd parts of N_mm(B),
+ * D_mm(B) = V - U and N_mm(B) = V + U, so r_m(B) - I = D^-1 (N - D) solves
+ *     (V - U) Z = 2 U
+ * (no cancellation for small B).  Powers by plain products; the system by
+ * Gaussian elimination with partial pivoting on all n right-hand sides.
+ * Returns 0, or -1 for a zero pivot. */
+static int pade_minus_identity(int n, const double *B, int m, work_t *w, double *Z)
+{
+    const int nn = n * n;
+    double c[14];
+    pade_coefs(m, c);
+    double *V = w->Bbar, *U = w->F, *cur = w->P[1], *nxt = w->P[2];
+    memset(V, 0, sizeof(double) * nn);
+    memset(U, 0, sizeof(double) * nn);
+    for (int i = 0; i < n; ++i) V[i * n + i] = c[0];
+    memcpy(cur, B, sizeof(double) * nn);
+    for (int j = 1; j <= m; ++j) {
+        if (j > 1) {
+            mat_mul(n, B, cur, nxt);
+            double *t = cur; cur = nxt; nxt = t;
+        }
+        double *acc = (j & 1) ? U : V;
+        for (int t = 0; t < nn; ++t) acc[t] += c[j] * cur[t];
+    }
+    double *M = w->T;
+    for (int t = 0; t < nn; ++t) {
+        M[t] = V[t] - U[t];
+        Z[t] = 2.0 * U[t];
+    }
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(M[i * n + k]) > fabs(M[p * n + k])) p = i;
+        if (M[p * n + k] == 0.0) return -1;
+        if (p != k) {
+            for (int j = 0; j < n; ++j) {
+                double t = M[k * n + j]; M[k * n + j] = M[p * n + j]; M[p * n + j] = t;
+                t = Z[k * n + j]; Z[k * n + j] = Z[p * n + j]; Z[p * n + j] = t;
+            }
+        }
+        for (int i = k + 1; i < n; ++i) {
+            const double f = M[i * n + k] / M[k * n + k];
+            for (int j = k; j < n; ++j) M[i * n + j] -= f * M[k * n + j];
+            for (int j = 0; j < n; ++j) Z[i * n + j] -= f * Z[k * n + j];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k)
+        for (int j = 0; j < n; ++j) {
+            double acc = Z[k * n + j];
+            for (int i = k + 1; i < n; ++i) acc -= M[k * n + i] * Z[i * n + j];
+            Z[k * n + j] = acc / M[k * n + k];
+        }
+    return 0;
+}
+
 /* option: Alg. 1 option (0, 1, 2), ORed with ORC_BOUND_TEST for the second
- * modification in the Taylor stage. */
+ * modification in the Taylor stage, or with ORC_PADE for the diagonal Pade
+ * scaling step instead of the Taylor one (Alg. 1 and K then unused). */
 static void expm_ws(int n, const double *A, double nrm, int K, int option,
                     int xform, double *Y, int *kms, work_t *w)
 {
     const int nn = n * n;
     const int bound_test = option & ORC_BOUND_TEST;
+    const int pade = option & ORC_PADE;
     option &= 3;
     int k, m, s;
-    orc_select(nrm, K, option, &k, &m, &s);
+    if (pade) {
+        k = 0;
+        orc_pade_select(nrm, &m, &s);
+    } else {
+        orc_select(nrm, K, option, &k, &m, &s);
+    }
     kms[0] = k; kms[1] = m; kms[2] = s;
 
     double *B = w->U;
     for (int t = 0; t < nn; ++t) B[t] = ldexp(A[t], -s);     /* 2^-s A */
 
-    taylor_minus_identity(n, B, TB_Q[k], TB_R[k], w, Y, bound_test, NULL);
+    if (pade) {
+        if (pade_minus_identity(n, B, m, w, Y) != 0)
+            for (int t = 0; t < nn; ++t) Y[t] = NAN;
+    } else {
+        taylor_minus_identity(n, B, TB_Q[k], TB_R[k], w, Y, bound_test, NULL);
+    }
 
     if (!xform) {
         /* Y-form squaring: (I+Y)^2 = I + 2Y + Y Y */
@@ -399,8 +517,8 @@ int orc_expm(int N, const double *A, double nrm, int K, int option, int xform,
              double *Y, int *kms)
 {
     const int n = N + 1;
-    if (n > ORC_NMAX || K < 1 || K > 9 || (option & ~ORC_BOUND_TEST) < 0 ||
-        (option & ~ORC_BOUND_TEST) > 2)
+    if (n > ORC_NMAX || K < 1 || K > 9 || (option & ~(ORC_BOUND_TEST | ORC_PADE)) < 0 ||
+        (option & ~(ORC_BOUND_TEST | ORC_PADE)) > 2)
         return -1;
     if (!isfinite(nrm)) return -1;
     work_t *w = (work_t *)malloc(sizeof(work_t));
@@ -424,7 +542,8 @@ int orc_apply_cells(int64_t C, int N, int D, int64_t ld, double dt, int K,
 {
     const int n = N + 1, nn = n * n;
     if (n > ORC_NMAX || D < 1 || D > 3 || ld < C) return -1;
-    if (K < 1 || K > 9 || (option & ~ORC_BOUND_TEST) < 0 || (option & ~ORC_BOUND_TEST) > 2)
+    if (K < 1 || K > 9 || (option & ~(ORC_BOUND_TEST | ORC_PADE)) < 0 ||
+        (option & ~(ORC_BOUND_TEST | ORC_PADE)) > 2)
         return -1;
     double *A = (double *)malloc(sizeof(double) * nn);
     double *Y = (double *)malloc(sizeof(double) * nn);

@@ -12,6 +12,8 @@
 /* option bit: Sastre's second modification (the bound test) in the Taylor
  * stage of orc_expm / orc_cell_expm / orc_apply_cells */
 #define ORC_BOUND_TEST 4
+/* option bit: the diagonal Pade scaling step (eq. PadeEqu) instead of Taylor */
+#define ORC_PADE 8
 
 #define ORC_NMAX 33 /* largest n = N+1 the oracle handles (N <= 32) */
 
@@ -32,6 +34,8 @@ int orc_expm(int N, const double *A, double nrm, int K, int option, int xform,
 int orc_cell_expm(int N, double dt, double rho_g, const double *rho_d,
                   const double *t_stop, int K, int option, int xform,
                   double *E, int *kms);
+int orc_pade_row(int i, int *m, double *theta, double *coef);
+void orc_pade_select(double nrm, int *mout, int *sout);
 int orc_taylor_stage(int n, const double *B, int k, int bound_test, double *F,
                      int *skipped, double *bexp_out);
 int orc_apply_cells(int64_t C, int N, int D, int64_t ld, double dt, int K,
