@@ -256,6 +256,7 @@ def main():
         res["batched_vs_plain"] = batched_measurement(torch, ops, workloads, dev)
         res["rk1_vs_expm"] = rk1_measurement(torch, ops, workloads, dev)
         res["bound_test"] = bound_test_measurement(torch, ops, _lib, workloads, dev)
+        res["pade_vs_taylor"] = pade_measurement(torch, ops, _lib, workloads, dev)
     if args.extra:
         res["extra"] = extra_measurements(torch, ops, workloads, dev)
     if not args.no_cpu_baseline:
@@ -491,6 +492,50 @@ def bound_test_measurement(torch, ops, _lib, workloads, dev):
         changed = int(((o1 - o2).abs().amax(dim=(0, 1)) > 0).sum())
         res[name] = {"mfma_ms": t0, "mfma_bound_test_ms": t1, "time_ratio": t1 / t0,
                      "cells_changed": changed, "n_cells": int(d["rho_g"].shape[0])}
+    return res
+
+
+def pade_measurement(torch, ops, _lib, workloads, dev, sample=128):
+    """The diagonal Pade scaling step (option bit DRAG_OPTION_PADE, MFMA
+    kernel) against the Taylor step: time (the default Taylor path, and the
+    Taylor step on the same MFMA kernel), mean degree and squarings from
+    drag_build, and the error against the exact exponential (long-double
+    eigen-decomposition) on the first `sample` cells."""
+    import oracle
+    res = {}
+    for name in ("n16_stiff_3d", "n8_adjoint_3d"):
+        d = workloads.make(name)
+        N = d["rho_d"].shape[0]
+        T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
+        o_t, o_w, o_p = (torch.empty_like(T["v"]) for _ in range(3))
+        t_default = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                        d["dt"], out=o_t), 20, 3)
+        try:
+            _lib.set_mapping(N, _lib.MAP_WAVE)
+            t_wave = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"],
+                                                         T["v"], d["dt"], out=o_w), 20, 3)
+        finally:
+            _lib.set_mapping(N, _lib.MAP_AUTO)
+        t_pade = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                     d["dt"], option=_lib.OPTION_PADE, out=o_p),
+                       20, 3)
+        row = {"n_cells": int(d["rho_g"].shape[0]), "taylor_default_ms": t_default,
+               "taylor_mfma_ms": t_wave, "pade_mfma_ms": t_pade,
+               "pade_over_taylor_mfma": t_pade / t_wave, "pade_over_taylor_default": t_pade / t_default}
+        for lab, opt in (("taylor", 2), ("pade", _lib.OPTION_PADE)):
+            _, _, _, kk, mm, ss = ops.build(T["rho_g"], T["rho_d"], T["t_stop"], d["dt"], option=opt)
+            row[f"{lab}_mean_m"] = float(mm.double().mean())
+            row[f"{lab}_mean_s"] = float(ss.double().mean())
+        v = d["v"][..., :sample]
+        exact = np.empty_like(v)
+        for c in range(sample):
+            E = oracle.truth_eigen(d["dt"], d["rho_g"][c], d["rho_d"][:, c], d["t_stop"][:, c])
+            exact[:, :, c] = v[:, :, c] @ E.T
+        scale = np.abs(v).max(axis=1)
+        for lab, o in (("taylor", o_t), ("pade", o_p)):
+            e = (np.abs(o[..., :sample].cpu().numpy() - exact).max(axis=1) / scale).max(axis=0)
+            row[f"{lab}_err_vs_exact"] = {"max": float(e.max()), "median": float(np.median(e))}
+        res[name] = row
     return res
 
 

@@ -106,6 +106,22 @@ typedef struct drag_desc {
  */
 #define DRAG_OPTION_BOUND_TEST 4
 
+/*
+ * option bit: the diagonal (m, m) Pade approximant of Sect. 2.3 (eq.
+ * PadeEqu, p = q = m) as the scaling step instead of the Taylor polynomial:
+ * m in {3, 5, 7, 9, 13} is the lowest degree whose theta_m covers
+ * ||dt K||_1, else m = 13 with the smallest s such that ||dt K||_1 / 2^s <=
+ * theta_13 (theta_m: the largest theta for which the backward error of r_m
+ * is below u, the criterion of eq. B8; drag_pade_row).  Each cell solves
+ * D_mm Z = N_mm - D_mm on its 16 x 16 tile (Gauss-Jordan with partial
+ * pivoting over the wavefront).  drag_expm_apply and drag_expm_steps run
+ * the MFMA kernel for every N; drag_build reports (k, m, s) = (0, m, s);
+ * the adjoint and the batched plan reject it, and so does combining it with
+ * DRAG_OPTION_BOUND_TEST (DRAG_ERR_OPTION).  Alg. 1's option bits and k_max
+ * are not used.
+ */
+#define DRAG_OPTION_PADE 8
+
 /* Fill `d` with the defaults: k_max = 9, option = 2, ld = n_cells. */
 void drag_desc_init(drag_desc *d, int64_t n_cells, int32_t n_species,
                     int32_t n_dim, double dt);
@@ -276,6 +292,10 @@ const char *drag_status_string(int code);
 
 /* Row k (1..9) of the library's copy of Table B.1 (Appendix B). */
 int drag_table_row(int k, int32_t *m, int32_t *q, int32_t *r, double *theta);
+/* Row 0..4 of the Pade scaling step's table: degree m, theta_m and the
+ * numerator coefficients c_0..c_m (coef may be NULL; the denominator's are
+ * (-1)^j c_j).  DRAG_ERR_OPTION for another row. */
+int drag_pade_row(int32_t row, int32_t *m, double *theta, double *coef);
 /* (k*, m*, s*) of Alg. 1 for a finite norm, computed on the host by the same
  * code the kernels run. */
 int drag_select(double norm, int32_t k_max, int32_t option, int32_t *k,

@@ -52,13 +52,14 @@ CELL_BAD_NORM = 8
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 K_AUTO = 0
 OPTION_BOUND_TEST = 4  # option bit: the second modification (bound test)
+OPTION_PADE = 8        # option bit: the diagonal Pade scaling step
 
 EXPORTS = [
     "drag_desc_init", "drag_build", "drag_expm_apply", "drag_expm_steps", "drag_rk1_apply", "drag_expm_apply_backward",
     "drag_plan_batched", "drag_plan_offsets", "drag_expm_apply_batched",
     "drag_plan_autotune", "drag_plan_config", "drag_plan_set_config", "drag_plan_destroy", "drag_get_status", "drag_clear_status", "drag_status_string",
     "drag_table_row", "drag_select", "drag_set_mapping", "drag_get_mapping",
-    "drag_set_k_max", "drag_get_k_max", "drag_plan_k_max",
+    "drag_set_k_max", "drag_get_k_max", "drag_plan_k_max", "drag_pade_row",
 ]
 
 
@@ -162,6 +163,8 @@ def lib():
     L.drag_set_k_max.restype = ctypes.c_int
     L.drag_get_k_max.argtypes = [i32, P(i32)]
     L.drag_get_k_max.restype = ctypes.c_int
+    L.drag_pade_row.argtypes = [i32, P(i32), P(ctypes.c_double), vp]
+    L.drag_pade_row.restype = ctypes.c_int
     L.drag_plan_k_max.argtypes = [vp, P(i32)]
     L.drag_plan_k_max.restype = ctypes.c_int
     _lib = L
@@ -207,6 +210,16 @@ def get_mapping(n_species: int) -> int:
     m = ctypes.c_int32()
     check(lib().drag_get_mapping(n_species, ctypes.byref(m)), "drag_get_mapping")
     return m.value
+
+
+def pade_row(row: int):
+    """(m, theta_m, numerator coefficients) of the library's Pade row 0..4."""
+    import numpy as np
+    m, th = ctypes.c_int32(), ctypes.c_double()
+    c = np.zeros(14)
+    check(lib().drag_pade_row(row, ctypes.byref(m), ctypes.byref(th),
+                              c.ctypes.data_as(ctypes.c_void_p)), "drag_pade_row")
+    return m.value, th.value, c[: m.value + 1].copy()
 
 
 def set_k_max(n_species: int, k_max: int) -> None:

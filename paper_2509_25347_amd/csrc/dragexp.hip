@@ -39,6 +39,7 @@ struct BuildArgs {
   int64_t n_cells, ld;
   double dt;
   int n_species, k_max, option;
+  int pade = 0;  // report the Pade scaling step's (m, s) instead of Alg. 1's
 };
 
 __global__ void __launch_bounds__(256) k_build(BuildArgs B, int xcd_blocks) {
@@ -75,7 +76,11 @@ __global__ void __launch_bounds__(256) k_build(BuildArgs B, int xcd_blocks) {
     if (B.a_out) B.a_out[i * ld + c] = bad ? qnan : sp.a;
     if (B.e_out) B.e_out[i * ld + c] = bad ? qnan : sp.e;
   }
-  const Kms km = bad ? Kms{0, 0, 0} : select_kms(nrm, B.k_max, B.option);
+  Kms km = bad ? Kms{0, 0, 0} : select_kms(nrm, B.k_max, B.option);
+  if (B.pade && !bad) {  // the Pade scaling step's (0, m, s)
+    const PadeSel ps = pade_select(nrm);
+    km = Kms{0, kPadeM[ps.row], ps.s};
+  }
   if (B.norm_out) B.norm_out[c] = bad ? qnan : nrm;
   if (B.k_out) B.k_out[c] = km.k;
   if (B.m_out) B.m_out[c] = km.m;
@@ -106,10 +111,10 @@ static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
   return hip_status(hipGetLastError());
 }
 
-template <int N, bool BT = false>
+template <int N, int METHOD = kStageTaylor>
 static int launch_forward_wave(const CellArgs& A, hipStream_t st) {
   const Grid gr = grid_for((A.n_cells + 15) / 16);  // a quad of cells per wavefront
-  hipLaunchKernelGGL((k_forward_wave<N, BT>), dim3(gr.blocks), dim3(256), 0, st, A,
+  hipLaunchKernelGGL((k_forward_wave<N, METHOD>), dim3(gr.blocks), dim3(256), 0, st, A,
                      gr.xcd_blocks);
   return hip_status(hipGetLastError());
 }
@@ -193,16 +198,20 @@ static FwdFn rk1_fwd(int N) {
   return tab[N - 1];
 }
 
-// The forward with Sastre's second modification in the Taylor stage (the
-// bound test): MFMA kernel for every N.
-static FwdFn wave_fwd_bound_test(int N) {
+// The MFMA forward with another scaling step, for every N: Sastre's second
+// modification in the Taylor stage (the bound test), or the diagonal Pade
+// approximant.
+template <int METHOD>
+static FwdFn wave_fwd_method(int N) {
   static const FwdFn tab[16] = {
-      launch_forward_wave<1, true>,  launch_forward_wave<2, true>,  launch_forward_wave<3, true>,
-      launch_forward_wave<4, true>,  launch_forward_wave<5, true>,  launch_forward_wave<6, true>,
-      launch_forward_wave<7, true>,  launch_forward_wave<8, true>,  launch_forward_wave<9, true>,
-      launch_forward_wave<10, true>, launch_forward_wave<11, true>, launch_forward_wave<12, true>,
-      launch_forward_wave<13, true>, launch_forward_wave<14, true>, launch_forward_wave<15, true>,
-      launch_forward_wave<16, true>};
+      launch_forward_wave<1, METHOD>,  launch_forward_wave<2, METHOD>,
+      launch_forward_wave<3, METHOD>,  launch_forward_wave<4, METHOD>,
+      launch_forward_wave<5, METHOD>,  launch_forward_wave<6, METHOD>,
+      launch_forward_wave<7, METHOD>,  launch_forward_wave<8, METHOD>,
+      launch_forward_wave<9, METHOD>,  launch_forward_wave<10, METHOD>,
+      launch_forward_wave<11, METHOD>, launch_forward_wave<12, METHOD>,
+      launch_forward_wave<13, METHOD>, launch_forward_wave<14, METHOD>,
+      launch_forward_wave<15, METHOD>, launch_forward_wave<16, METHOD>};
   return tab[N - 1];
 }
 
@@ -278,8 +287,10 @@ static int check_desc(const drag_desc* d) {
   if (d->ld > (INT64_MAX / 64)) return DRAG_ERR_LD;
   if (!(d->dt >= 0.0) || !isfinite(d->dt)) return DRAG_ERR_DT;
   if (d->k_max < DRAG_K_AUTO || d->k_max > 9) return DRAG_ERR_K_MAX;
-  const int opt = d->option & ~DRAG_OPTION_BOUND_TEST;
+  const int opt = d->option & ~(DRAG_OPTION_BOUND_TEST | DRAG_OPTION_PADE);
   if (opt < 0 || opt > 2) return DRAG_ERR_OPTION;
+  if ((d->option & DRAG_OPTION_BOUND_TEST) && (d->option & DRAG_OPTION_PADE))
+    return DRAG_ERR_OPTION;
   return DRAG_OK;
 }
 
@@ -637,6 +648,7 @@ int drag_build(const drag_desc* d, const double* rho_g, const double* rho_d,
       if (overlap(out[x], out[y])) return DRAG_ERR_ALIAS;
   BuildArgs B{rho_g, rho_d, t_stop, a_out, e_out, norm_out, k_out, m_out, s_out,
               C,     ld,    d->dt,  (int)N, k_for(d->k_max, (int)N), d->option & 3};
+  B.pade = (d->option & DRAG_OPTION_PADE) ? 1 : 0;
   const Grid gr = grid_for((C + 255) / 256);
   hipLaunchKernelGGL(k_build, dim3(gr.blocks), dim3(256), 0, (hipStream_t)stream, B,
                      gr.xcd_blocks);
@@ -659,7 +671,10 @@ int drag_expm_apply(const drag_desc* d, const double* rho_g, const double* rho_d
     return DRAG_ERR_ALIAS;
   CellArgs A{rho_g, rho_d, t_stop, v_in, v_out, C,
              ld,    d->dt, (int)D, k_for(d->k_max, (int)N), d->option & 3};
-  if (d->option & DRAG_OPTION_BOUND_TEST) return wave_fwd_bound_test((int)N)(A, (hipStream_t)stream);
+  if (d->option & DRAG_OPTION_PADE)
+    return wave_fwd_method<kStagePade>((int)N)(A, (hipStream_t)stream);
+  if (d->option & DRAG_OPTION_BOUND_TEST)
+    return wave_fwd_method<kStageTaylorBound>((int)N)(A, (hipStream_t)stream);
   const int map = mapping_for((int)N);
   return map == DRAG_MAP_LANE ? lane_fwd((int)N)(A, (hipStream_t)stream)
                               : wave_fwd((int)N)(A, (hipStream_t)stream);
@@ -747,8 +762,8 @@ int drag_expm_apply_backward(const drag_desc* d, const double* rho_g, const doub
     for (int y = x + 1; y < 6; ++y)
       if (overlap(out[x], out[y])) return DRAG_ERR_ALIAS;
   }
-  // the adjoint differentiates the evaluation without the bound test
-  if (d->option & DRAG_OPTION_BOUND_TEST) return DRAG_ERR_OPTION;
+  // the adjoint differentiates the Taylor evaluation without the bound test
+  if (d->option & (DRAG_OPTION_BOUND_TEST | DRAG_OPTION_PADE)) return DRAG_ERR_OPTION;
   BackArgs B{rho_g, rho_d, t_stop, v_in, w, v_out, g_v, g_logt, g_t, g_rho_d, g_rho_g,
              C,     ld,    d->dt,  (int)D, k_for(d->k_max, (int)N), d->option};
   const int map = mapping_for_bwd((int)N);
@@ -989,6 +1004,15 @@ int drag_select(double norm, int32_t k_max, int32_t option, int32_t* k, int32_t*
   if (k) *k = r.k;
   if (m) *m = r.m;
   if (s) *s = r.s;
+  return DRAG_OK;
+}
+
+int drag_pade_row(int32_t row, int32_t* m, double* theta, double* coef) {
+  if (row < 0 || row >= kPadeRows) return DRAG_ERR_OPTION;
+  if (m) *m = kPadeM[row];
+  if (theta) *theta = kPadeTheta[row];
+  if (coef)
+    for (int j = 0; j <= kPadeM[row]; ++j) coef[j] = kPadeC[row][j];
   return DRAG_OK;
 }
 

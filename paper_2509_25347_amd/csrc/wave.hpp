@@ -266,6 +266,8 @@ __device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const 
   }
 }
 
+#include "pade.hpp"  // the Pade scaling step, built on the helpers above
+
 // One squaring of the Y form, Z <- 2 Z + Z Z, issued as (Z + 2 I) Z: Z is
 // staged, lanes 0..15 add 2 to the diagonal of the staged copy, the copy is
 // read back as the A operand, Z itself is the B operand and the accumulator
@@ -289,6 +291,10 @@ __device__ __forceinline__ v4d square_step(const v4d& Z, double* stage, int g, i
 // j): loads, coefficients (Eq. 2: a = dt / t, e = rho_i / rho_g, p = e a),
 // ||A||_1 and Alg. 1.  The coefficients go to the quad's LDS tables (q*),
 // species j >= N as zeros; the per-cell values come back row-uniform.
+constexpr int kStageTaylor = 0;
+constexpr int kStageTaylorBound = 1;
+constexpr int kStagePade = 2;
+
 struct QuadCell {
   unsigned bad;  // bad-input bits of the row's cell
   int kpack;     // k* | s* << 4
@@ -299,7 +305,7 @@ __device__ __forceinline__ QuadCell quad_setup(const double* rho_g, const double
                                                const double* t_stop, int64_t n_cells, int64_t ld,
                                                double dt, int K, int option, const int N,
                                                int64_t c0, int g, int j, double* qa, double* qe,
-                                               double* qp) {
+                                               double* qp, bool pade = false) {
   const int64_t cg = c0 + g;
   double aj = 0.0, ej = 0.0, pj = 0.0;
   unsigned bad = 0;
@@ -329,8 +335,13 @@ __device__ __forceinline__ QuadCell quad_setup(const double* rho_g, const double
   Q.sig = row_chain(1.0, ej, N);
   if ((bad & 0xffu) == 0u && ((bad & kNonFinite) || !isfinite(nrm))) bad = kBadNorm;
   Q.bad = bad & 0xffu;
-  const Kms km = select_kms(Q.bad ? 0.0 : nrm, K, option);
-  Q.kpack = km.k | (km.s << 4);
+  if (pade) {  // the Pade table row instead of k*
+    const PadeSel ps = pade_select(Q.bad ? 0.0 : nrm);
+    Q.kpack = ps.row | (ps.s << 4);
+  } else {
+    const Kms km = select_kms(Q.bad ? 0.0 : nrm, K, option);
+    Q.kpack = km.k | (km.s << 4);
+  }
   const int slot = 16 * g + quad_slot(j);
   qa[slot] = aj;
   qe[slot] = ej;
@@ -341,8 +352,9 @@ __device__ __forceinline__ QuadCell quad_setup(const double* rho_g, const double
 
 // With store = false the outputs stay in the quad's LDS block (vs) for the
 // workgroup to store (group_store).
-// BT: the Taylor stage with the second modification (bound test).
-template <bool BT = false>
+// METHOD: the scaling step (kStageTaylor, kStageTaylorBound: with the
+// second modification, kStagePade: the diagonal Pade approximant).
+template <int METHOD = kStageTaylor>
 __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N, int64_t c0,
                                                   int lane, double* lds, bool store = true) {
   const int g = lane >> 4, j = lane & 15;
@@ -355,7 +367,7 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
   double* qp = qe + 64;
 
   const QuadCell Q = quad_setup(A.rho_g, A.rho_d, A.t_stop, A.n_cells, ld, A.dt, A.k_max,
-                                A.option, N, c0, g, j, qa, qe, qp);
+                                A.option, N, c0, g, j, qa, qe, qp, METHOD == kStagePade);
   // the four cells' bad bits, (k*, s*) and 1 / sigma as scalars
   const double rsig = 1.0 / Q.sig;
   unsigned bad_s[4];
@@ -418,7 +430,7 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
       continue;
     }
     const int kp = c == 0 ? kp_s[0] : c == 1 ? kp_s[1] : c == 2 ? kp_s[2] : kp_s[3];
-    const int kk = kp & 15, s = kp >> 4;
+    const int kk = kp & 15, s = kp >> 4;  // kk: k*, or the Pade table row
     const int q = kPsQ[kk], r = kPsR[kk], m = kTabM[kk];
     const double crsig = c == 0 ? rsig_s[0] : c == 1 ? rsig_s[1] : c == 2 ? rsig_s[2] : rsig_s[3];
 
@@ -446,11 +458,16 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
       M[v] = fma(dg, R.nbj, R.npbj * rm[v]);
     }
     v4d Z;
-    switch (q) {  // uniform; one code path per power count
-      case 2: Z = quad_poly<2, BT>(M, R, rm, m, r, stage, g, j); break;
-      case 3: Z = quad_poly<3, BT>(M, R, rm, m, r, stage, g, j); break;
-      case 4: Z = quad_poly<4, BT>(M, R, rm, m, r, stage, g, j); break;
-      default: Z = quad_poly<5, BT>(M, R, rm, m, r, stage, g, j); break;
+    constexpr bool BT = METHOD == kStageTaylorBound;
+    if constexpr (METHOD == kStagePade) {
+      Z = pade_stage(M, R, rm, kk, N, stage, g, j);
+    } else {
+      switch (q) {  // uniform; one code path per power count
+        case 2: Z = quad_poly<2, BT>(M, R, rm, m, r, stage, g, j); break;
+        case 3: Z = quad_poly<3, BT>(M, R, rm, m, r, stage, g, j); break;
+        case 4: Z = quad_poly<4, BT>(M, R, rm, m, r, stage, g, j); break;
+        default: Z = quad_poly<5, BT>(M, R, rm, m, r, stage, g, j); break;
+      }
     }
 
     // squarings Z <- (Z + 2 I) Z, two per trip so that the result and
@@ -512,8 +529,9 @@ __device__ __forceinline__ void group_store(const CellArgs& A, const int N, int6
   }
 }
 
-template <int N, bool BT = false>
-__global__ void __launch_bounds__(256, BT ? 4 : 5) k_forward_wave(CellArgs A, int xcd_blocks) {
+template <int N, int METHOD = kStageTaylor>
+__global__ void __launch_bounds__(256, METHOD == kStageTaylor ? 5 : 4)
+    k_forward_wave(CellArgs A, int xcd_blocks) {
   __shared__ double lds[4 * kQuadDoubles];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -522,7 +540,7 @@ __global__ void __launch_bounds__(256, BT ? 4 : 5) k_forward_wave(CellArgs A, in
   const int64_t g0 = logical * 16;  // the workgroup's first cell
   if (g0 >= A.n_cells) return;     // uniform over the workgroup
   const int64_t c0 = g0 + 4 * w;
-  if (c0 < A.n_cells) wave_forward_quad<BT>(A, N, c0, lane, lds + w * kQuadDoubles, false);
+  if (c0 < A.n_cells) wave_forward_quad<METHOD>(A, N, c0, lane, lds + w * kQuadDoubles, false);
   __syncthreads();
   group_store(A, N, g0, lds);
 }

@@ -75,7 +75,7 @@ def test_argument_errors_return_before_launch(L):
     assert _apply(L, mk(k_max=10), base) == _lib.ERR_K_MAX
     assert _apply(L, mk(option=3), base) == _lib.ERR_OPTION
     assert _apply(L, mk(option=3 | _lib.OPTION_BOUND_TEST), base) == _lib.ERR_OPTION
-    assert _apply(L, mk(option=8), base) == _lib.ERR_OPTION
+    assert _apply(L, mk(option=16), base) == _lib.ERR_OPTION
     assert _apply(L, mk(), [1 << 20, 0, 3 << 20, 4 << 20, 8 << 20]) == _lib.ERR_NULL_POINTER
     # v_out overlapping rho_d (not the allowed in-place v_in)
     assert _apply(L, mk(), [1 << 20, 2 << 20, 3 << 20, 4 << 20, (2 << 20) + 8]) == _lib.ERR_ALIAS
@@ -153,6 +153,31 @@ def test_mapping_controls(L):
         _lib.set_mapping(12, _lib.MAP_LANE)
     with pytest.raises(_lib.DragError):
         _lib.set_mapping(0, _lib.MAP_WAVE)
+
+
+def test_pade_table_matches_oracle(L, orc):
+    """The library's Pade rows (degree, theta, coefficients) equal the
+    oracle's bit for bit (each side has its own copy)."""
+    for i in range(5):
+        m, th, c = _lib.pade_row(i)
+        mo, tho, co = orc.pade_row(i)
+        assert (m, th) == (mo, tho)
+        assert np.array_equal(c, co)
+    with pytest.raises(_lib.DragError):
+        _lib.pade_row(5)
+
+
+def test_pade_option_errors(L):
+    def mk(opt):
+        return _lib.make_desc(10, 4, 3, 10, 1.0, 9, opt)
+    base = [1 << 20, 2 << 20, 3 << 20, 4 << 20, 5 << 20]
+    both = _lib.OPTION_PADE | _lib.OPTION_BOUND_TEST | 2
+    assert _apply(L, mk(both), base) == _lib.ERR_OPTION
+    assert _apply(L, mk(_lib.OPTION_PADE | 3), base) == _lib.ERR_OPTION
+    ptrs = [ctypes.c_void_p(x) for x in base]
+    outs = [ctypes.c_void_p(x) for x in (6 << 20, 7 << 20, 8 << 20, 9 << 20, 10 << 20, 11 << 20)]
+    d = mk(_lib.OPTION_PADE)
+    assert L.drag_expm_apply_backward(ctypes.byref(d), *ptrs, *outs, None) == _lib.ERR_OPTION
 
 
 def test_taylor_cap_controls(L):

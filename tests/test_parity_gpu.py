@@ -239,6 +239,52 @@ def test_bound_test_option(ops, dev, orc, case):
         assert changed >= 1, case
 
 
+@pytest.mark.parametrize("case", ["n1_closed_form", "n4_3d", "n8_jittered", "n5_stiff", "n12_stiff",
+                                  "n16_stiff_3d"])
+def test_pade_option(ops, dev, orc, case):
+    """option = OPTION_PADE (the diagonal Pade scaling step on the MFMA kernel):
+    the same (0, m, s) as the oracle's Pade selection, within the oracle's
+    bar (its dense Pade step) and the exact exponential's 1e-13; a ragged
+    cell count leaves quads cut short."""
+    from paper_2509_25347_amd import _lib
+    d = {"n8_jittered": lambda: W.make_jittered(8, 701), "n5_stiff": lambda: W.make_stiff(5, 701),
+         "n12_stiff": lambda: W.make_stiff(12, 701)}.get(case, lambda: W.make(case, 701))()
+    T = _to(d, dev)
+    got = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"],
+                         option=_lib.OPTION_PADE)
+    _, _, nrm_gpu, kk, mm, ss = ops.build(T["rho_g"], T["rho_d"], T["t_stop"], d["dt"],
+                                          option=_lib.OPTION_PADE)
+    torch.cuda.synchronize()
+    ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"],
+                                        option=orc.PADE)
+    assert st == 0
+    assert np.array_equal(kk.cpu().numpy(), kms[0]) and np.array_equal(mm.cpu().numpy(), kms[1])
+    assert np.array_equal(ss.cpu().numpy(), kms[2])
+    g = got.cpu().numpy()
+    assert_parity(g, ref, nrm, d, case)
+    et = cell_errors(g, truth_apply(d), d["v"])
+    assert np.nanmax(et) <= 1e-13, np.nanmax(et)
+    assert momentum_errors(g, d).max() <= 1e-12
+
+
+def test_pade_dt_zero_and_bad_cells(ops, dev, orc):
+    from paper_2509_25347_amd import _lib
+    d = W.make("n16_stiff_3d", 64)
+    T = _to(d, dev)
+    out = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], 0.0, option=_lib.OPTION_PADE)
+    assert torch.equal(out, T["v"])
+    rg, ts, v = d["rho_g"].copy(), d["t_stop"].copy(), d["v"].copy()
+    rg[3] = -1.0
+    ts[5, 9] = 0.0
+    v[1, 2, 17] = np.inf
+    ref, kms, nrm, st = orc.apply_cells(rg, d["rho_d"], ts, v, 1.0, option=orc.PADE)
+    ops.clear_status()
+    got = run(ops, dict(rho_g=rg, rho_d=d["rho_d"], t_stop=ts, v=v, dt=1.0), dev,
+              option=_lib.OPTION_PADE)
+    assert ops.get_status() == st
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+
+
 def test_dt_zero_identity_and_in_place(ops, dev):
     for name in ("n4_3d", "n16_stiff_3d"):
         d = W.make(name, 1000)
