@@ -22,7 +22,11 @@
  *     t_stop [N][ld]             stopping times T_s,i         t_stop[i*ld + c]
  *     v      [D][N+1][ld]        velocities, row 0 = gas      v[(d*(N+1) + j)*ld + c]
  * with N = n_species in [1, 16] and D = n_dim in [1, 3]; the D components
- * share one matrix K.
+ * share one matrix K.  drag_build, drag_expm_apply and drag_expm_steps also
+ * take N = 17..32 (a large-N kernel: one cell per wavefront on 2 x 2 blocks
+ * of MFMA tiles, the plain Taylor step, K_AUTO = 9; built for cases such as
+ * the paper's 20-species Collisions test, not tuned); the other calls
+ * return DRAG_ERR_N_SPECIES above 16.
  *
  * Ownership and synchronisation: every array pointer is a device pointer
  * owned by the caller.  drag_build, drag_expm_apply, drag_expm_apply_backward
@@ -81,7 +85,7 @@ typedef void *drag_stream_t;
 
 typedef struct drag_desc {
     int64_t n_cells;   /* C >= 0; C = 0 is a no-op */
-    int32_t n_species; /* N in [1, 16] */
+    int32_t n_species; /* N in [1, 16]; up to 32 for the forward calls */
     int32_t n_dim;     /* D in [1, 3] */
     int64_t ld;        /* leading dimension of every [.][ld] array, >= C */
     double dt;         /* finite, >= 0; dt = 0 returns v unchanged, bit for bit */

@@ -20,6 +20,7 @@
 #include "pair.hpp"
 #include "batched.hpp"
 #include "rk1.hpp"
+#include "big.hpp"
 
 namespace dragexp {
 
@@ -123,6 +124,13 @@ template <int N>
 static int launch_rk1(const CellArgs& A, hipStream_t st) {
   const Grid gr = grid_for((A.n_cells + 255) / 256);
   hipLaunchKernelGGL(k_rk1_lane<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
+// N = 17..32: one cell per wavefront, four per workgroup
+static int launch_forward_big(const CellArgs& A, int N, hipStream_t st) {
+  const Grid gr = grid_for((A.n_cells + 3) / 4);
+  hipLaunchKernelGGL(k_forward_big, dim3(gr.blocks), dim3(256), 0, st, A, N, gr.xcd_blocks);
   return hip_status(hipGetLastError());
 }
 
@@ -272,15 +280,18 @@ static int g_kmax_override[16] = {0};
 
 static int k_for(int k_max, int N) {
   if (k_max != DRAG_K_AUTO) return k_max;
+  if (N > kMaxSpecies) return 9;  // the large-N kernel: not tuned
   const int o = g_kmax_override[N - 1];
   return o ? o : g_default_kmax[N - 1];
 }
 
 // ---- argument checks -------------------------------------------------------------
-static int check_desc(const drag_desc* d) {
+// max_species: 16 (one MFMA tile), or 32 for the entry points that have the
+// large-N forward kernel (drag_build, drag_expm_apply, drag_expm_steps).
+static int check_desc(const drag_desc* d, int max_species = kMaxSpecies) {
   if (!d) return DRAG_ERR_NULL_DESC;
   if (d->n_cells < 0) return DRAG_ERR_N_CELLS;
-  if (d->n_species < 1 || d->n_species > kMaxSpecies) return DRAG_ERR_N_SPECIES;
+  if (d->n_species < 1 || d->n_species > max_species) return DRAG_ERR_N_SPECIES;
   if (d->n_dim < 1 || d->n_dim > 3) return DRAG_ERR_N_DIM;
   if (d->ld < d->n_cells || d->ld < 1) return DRAG_ERR_LD;
   // every index (row * ld + c) must fit in int64 with room to spare
@@ -629,7 +640,7 @@ void drag_desc_init(drag_desc* d, int64_t n_cells, int32_t n_species, int32_t n_
 int drag_build(const drag_desc* d, const double* rho_g, const double* rho_d,
                const double* t_stop, double* a_out, double* e_out, double* norm_out,
                int32_t* k_out, int32_t* m_out, int32_t* s_out, drag_stream_t stream) {
-  int rc = check_desc(d);
+  int rc = check_desc(d, kBigMaxSpecies);
   if (rc) return rc;
   if (d->n_cells == 0) return DRAG_OK;
   if (!rho_g || !rho_d || !t_stop) return DRAG_ERR_NULL_POINTER;
@@ -658,7 +669,7 @@ int drag_build(const drag_desc* d, const double* rho_g, const double* rho_d,
 int drag_expm_apply(const drag_desc* d, const double* rho_g, const double* rho_d,
                     const double* t_stop, const double* v_in, double* v_out,
                     drag_stream_t stream) {
-  int rc = check_desc(d);
+  int rc = check_desc(d, kBigMaxSpecies);
   if (rc) return rc;
   if (d->n_cells == 0) return DRAG_OK;
   if (!rho_g || !rho_d || !t_stop || !v_in || !v_out) return DRAG_ERR_NULL_POINTER;
@@ -671,6 +682,10 @@ int drag_expm_apply(const drag_desc* d, const double* rho_g, const double* rho_d
     return DRAG_ERR_ALIAS;
   CellArgs A{rho_g, rho_d, t_stop, v_in, v_out, C,
              ld,    d->dt, (int)D, k_for(d->k_max, (int)N), d->option & 3};
+  if (N > kMaxSpecies) {  // the large-N kernel has the plain Taylor step only
+    if (d->option & (DRAG_OPTION_PADE | DRAG_OPTION_BOUND_TEST)) return DRAG_ERR_OPTION;
+    return launch_forward_big(A, (int)N, (hipStream_t)stream);
+  }
   if (d->option & DRAG_OPTION_PADE)
     return wave_fwd_method<kStagePade>((int)N)(A, (hipStream_t)stream);
   if (d->option & DRAG_OPTION_BOUND_TEST)
@@ -701,7 +716,7 @@ int drag_rk1_apply(const drag_desc* d, const double* rho_g, const double* rho_d,
 int drag_expm_steps(const drag_desc* d, const double* rho_g, const double* rho_d,
                     const double* t_stop, const double* v_in, double* v_out, int64_t n_steps,
                     double* history, drag_stream_t stream) {
-  int rc = check_desc(d);
+  int rc = check_desc(d, kBigMaxSpecies);
   if (rc) return rc;
   if (n_steps < 0) return DRAG_ERR_STEPS;
   if (d->n_cells == 0 || n_steps == 0) {
@@ -971,7 +986,7 @@ const char* drag_status_string(int code) {
     case DRAG_OK: return "ok";
     case DRAG_ERR_NULL_DESC: return "descriptor pointer is NULL";
     case DRAG_ERR_N_CELLS: return "n_cells < 0";
-    case DRAG_ERR_N_SPECIES: return "n_species outside [1, 16]";
+    case DRAG_ERR_N_SPECIES: return "n_species outside [1, 16] (or [1, 32] for the forward calls)";
     case DRAG_ERR_N_DIM: return "n_dim outside [1, 3]";
     case DRAG_ERR_STEPS: return "n_steps < 0, or the history would overflow 64-bit offsets";
     case DRAG_ERR_LD: return "ld < n_cells or ld too large";

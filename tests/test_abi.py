@@ -64,7 +64,7 @@ def test_argument_errors_return_before_launch(L):
     assert _apply(L, None, base) == _lib.ERR_NULL_DESC
     assert _apply(L, mk(n_cells=-1), base) == _lib.ERR_N_CELLS
     assert _apply(L, mk(n_species=0), base) == _lib.ERR_N_SPECIES
-    assert _apply(L, mk(n_species=17), base) == _lib.ERR_N_SPECIES
+    assert _apply(L, mk(n_species=33), base) == _lib.ERR_N_SPECIES
     assert _apply(L, mk(n_dim=0), base) == _lib.ERR_N_DIM
     assert _apply(L, mk(n_dim=4), base) == _lib.ERR_N_DIM
     assert _apply(L, mk(ld=9), base) == _lib.ERR_LD
@@ -90,6 +90,9 @@ def test_backward_argument_errors(L):
     assert L.drag_expm_apply_backward(None, *nul) == _lib.ERR_NULL_DESC
     bad = _lib.make_desc(10, 20, 3, 10, 1.0)
     assert L.drag_expm_apply_backward(ctypes.byref(bad), *nul) == _lib.ERR_N_SPECIES
+    # the forward goes to 32 species, the adjoint stops at 16
+    bad17 = _lib.make_desc(10, 17, 3, 10, 1.0)
+    assert L.drag_expm_apply_backward(ctypes.byref(bad17), *nul) == _lib.ERR_N_SPECIES
     assert L.drag_expm_apply_backward(ctypes.byref(d), *nul) == _lib.ERR_NULL_POINTER
     # the adjoint takes no bound test (checked before anything is enqueued)
     bt = _lib.make_desc(10, 4, 3, 10, 1.0, 9, 2 | _lib.OPTION_BOUND_TEST)
@@ -174,6 +177,11 @@ def test_pade_option_errors(L):
     both = _lib.OPTION_PADE | _lib.OPTION_BOUND_TEST | 2
     assert _apply(L, mk(both), base) == _lib.ERR_OPTION
     assert _apply(L, mk(_lib.OPTION_PADE | 3), base) == _lib.ERR_OPTION
+    # the large-N forward (17..32 species) has the plain Taylor step only
+    big = _lib.make_desc(10, 20, 3, 10, 1.0, 9, 2 | _lib.OPTION_PADE)
+    assert _apply(L, big, base) == _lib.ERR_OPTION
+    big = _lib.make_desc(10, 20, 3, 10, 1.0, 9, 2 | _lib.OPTION_BOUND_TEST)
+    assert _apply(L, big, base) == _lib.ERR_OPTION
     ptrs = [ctypes.c_void_p(x) for x in base]
     outs = [ctypes.c_void_p(x) for x in (6 << 20, 7 << 20, 8 << 20, 9 << 20, 10 << 20, 11 << 20)]
     d = mk(_lib.OPTION_PADE)

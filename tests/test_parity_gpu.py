@@ -285,6 +285,40 @@ def test_pade_dt_zero_and_bad_cells(ops, dev, orc):
     assert np.array_equal(np.isnan(got), np.isnan(ref))
 
 
+@pytest.mark.parametrize("N", [17, 20, 24, 32])
+def test_large_n_forward(ops, dev, orc, N):
+    """N = 17..32 (the large-N kernel: 2 x 2 blocks of MFMA tiles, one cell
+    per wavefront): (k*, m*, s*) bit-exact, the oracle's bar and the exact
+    exponential's 1e-13, momentum, a ragged cell count, K_AUTO, bad cells."""
+    from paper_2509_25347_amd import _lib
+    for mk in (W.make_stiff, W.make_jittered):
+        d = mk(N, 203)
+        T = _to(d, dev)
+        got = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"])
+        _, _, _, kk, mm, ss = ops.build(T["rho_g"], T["rho_d"], T["t_stop"], d["dt"])
+        torch.cuda.synchronize()
+        ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"])
+        assert np.array_equal(np.stack([x.cpu().numpy() for x in (kk, mm, ss)]), kms)
+        g = got.cpu().numpy()
+        assert_parity(g, ref, nrm, d, f"N={N} {mk.__name__}")
+        et = cell_errors(g, truth_apply(d), d["v"])
+        assert np.nanmax(et) <= 1e-13, np.nanmax(et)
+        assert momentum_errors(g, d).max() <= 1e-12
+        auto = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"],
+                              k_max=_lib.K_AUTO)
+        assert torch.equal(auto, got)  # K_AUTO is 9 above 16 species
+    d = W.make_stiff(N, 40)
+    rg, ts, v = d["rho_g"].copy(), d["t_stop"].copy(), d["v"].copy()
+    rg[3] = 0.0
+    ts[N - 1, 9] = np.nan
+    v[2, N, 17] = -np.inf
+    ref, kms, nrm, st = orc.apply_cells(rg, d["rho_d"], ts, v, 1.0)
+    ops.clear_status()
+    got = run(ops, dict(rho_g=rg, rho_d=d["rho_d"], t_stop=ts, v=v, dt=1.0), dev)
+    assert ops.get_status() == st
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+
+
 def test_dt_zero_identity_and_in_place(ops, dev):
     for name in ("n4_3d", "n16_stiff_3d"):
         d = W.make(name, 1000)
