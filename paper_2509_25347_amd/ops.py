@@ -72,12 +72,21 @@ def _shapes(rho_g, rho_d, t_stop, v):
     return C, N, D, max(ld, C) if C else max(ld, 1)
 
 
+def _out_like(v, C, ld):
+    """An output with v's shape and the shared leading dimension ld (the
+    library addresses every [.][ld] array with the one ld of the descriptor)."""
+    if ld == C:
+        return torch.empty(tuple(v.shape), dtype=v.dtype, device=v.device)
+    full = torch.empty(tuple(v.shape[:-1]) + (ld,), dtype=v.dtype, device=v.device)
+    return full[..., :C]
+
+
 def expm_apply(rho_g, rho_d, t_stop, v, dt, k_max=9, option=2, out=None, stream=None):
     """v' = exp(dt K) v for every cell (drag_expm_apply).  ``out`` may be
     ``v`` itself (in place)."""
     C, N, D, ld = _shapes(rho_g, rho_d, t_stop, v)
     if out is None:
-        out = torch.empty_like(v)
+        out = _out_like(v, C, ld)
     else:
         _require(out, "out")
         if out.shape != v.shape or _ld_of(out, 2, "out") not in (None, ld) and C:
@@ -94,7 +103,7 @@ def rk1_apply(rho_g, rho_d, t_stop, v, dt, out=None, stream=None):
     by its O(N) closed form (drag_rk1_apply).  ``out`` may be ``v`` itself."""
     C, N, D, ld = _shapes(rho_g, rho_d, t_stop, v)
     if out is None:
-        out = torch.empty_like(v)
+        out = _out_like(v, C, ld)
     else:
         _require(out, "out")
         if out.shape != v.shape or _ld_of(out, 2, "out") not in (None, ld) and C:

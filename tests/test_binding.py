@@ -1,0 +1,30 @@
+"""Host-side checks of the Python binding (no GPU needed): outputs it
+allocates share the caller's leading dimension, since the library addresses
+every [.][ld] array with the one ld of the descriptor."""
+import pytest
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("C,pad", [(63, 0), (63, 1), (1000, 24), (5, 64)])
+def test_out_like_keeps_the_leading_dimension(C, pad):
+    from paper_2509_25347_amd import ops
+    ld = C + pad
+    full = torch.zeros((3, 5, ld), dtype=torch.float64)
+    v = full[..., :C]
+    out = ops._out_like(v, C, ld)
+    assert out.shape == v.shape and out.stride() == v.stride()
+    # the last element the library writes, (rows - 1) * ld + C - 1, lies in the storage
+    rows = 3 * 5
+    assert out.untyped_storage().nbytes() >= 8 * ((rows - 1) * ld + C)
+    assert ops._ld_of(out, 2, "out") == ld
+
+
+def test_layout_helpers_reject_uneven_rows():
+    from paper_2509_25347_amd import ops
+    x = torch.zeros((3, 5, 40), dtype=torch.float64)[:, :, ::2]
+    with pytest.raises(ValueError):
+        ops._ld_of(x, 2, "x")
+    y = torch.zeros((3, 6, 40), dtype=torch.float64)[:, :5, :]  # rows spaced 40, blocks 240
+    with pytest.raises(ValueError):
+        ops._ld_of(y, 2, "y")

@@ -1,0 +1,138 @@
+"""Seeded random cases of the forward, the backward Euler step and the
+variants on the GPU against the oracle (tests marked gpu): random species
+count, cell count (ragged against every launch granularity), leading
+dimension, component count, time step over twelve decades, Alg. 1 cap and
+option, mapping, and inputs with decoupled species (t = inf), dust-free
+species (rho_d = 0) and a few bad cells mixed in.  The bars are those of the
+dedicated parity tests: the oracle's max(1e-13, 4 u ||dt K||_1) per cell for
+the exponential, (4N + 16) u for RK1; status bits and NaN cells exactly."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_25347_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+def random_case(rng):
+    N = int(rng.integers(1, 17))
+    C = int(rng.choice([1, 2, 3, 5, 15, 17, 63, 65, 255, 257, 511, 700, 1333]))
+    D = int(rng.integers(1, 4))
+    ld = C + int(rng.choice([0, 0, 1, 7, 64]))
+    dt = float(10.0 ** rng.uniform(-6, 6))
+    rho_g = rng.uniform(0.1, 10.0, C)
+    eps = 10.0 ** rng.uniform(-4, 1, (N, C))
+    rho_d = eps * rho_g[None]
+    t_stop = 10.0 ** rng.uniform(-4, 3, (N, C))
+    v = rng.standard_normal((D, N + 1, C)) * 10.0 ** rng.uniform(-2, 2)
+    # structure: decoupled and dust-free species, a few bad cells
+    m = rng.random((N, C))
+    t_stop[m < 0.05] = np.inf
+    rho_d[(m > 0.05) & (m < 0.1)] = 0.0
+    bad = []
+    if C >= 5 and rng.random() < 0.5:
+        cells = rng.choice(C, size=min(3, C), replace=False)
+        kinds = rng.integers(0, 4, len(cells))
+        for c, k in zip(cells, kinds):
+            if k == 0:
+                rho_g[c] = -1.0
+            elif k == 1:
+                t_stop[rng.integers(N), c] = 0.0
+            elif k == 2:
+                v[rng.integers(D), rng.integers(N + 1), c] = np.nan
+            else:
+                rho_d[rng.integers(N), c] = np.inf
+            bad.append(int(c))
+    return dict(N=N, C=C, D=D, ld=ld, dt=dt, rho_g=rho_g, rho_d=rho_d, t_stop=t_stop, v=v)
+
+
+def to_dev(case, dev):
+    C, ld = case["C"], case["ld"]
+
+    def pad(x):
+        y = np.full(x.shape[:-1] + (ld,), np.nan)
+        y[..., :C] = x
+        return torch.from_numpy(y).to(dev)[..., :C]
+
+    return (torch.from_numpy(case["rho_g"]).to(dev), pad(case["rho_d"]), pad(case["t_stop"]),
+            pad(case["v"]))
+
+
+def cell_errors(got, ref, v_in):
+    scale = np.abs(v_in).max(axis=1)
+    scale = np.where((scale == 0) | ~np.isfinite(scale), 1.0, scale)
+    return (np.abs(got - ref).max(axis=1) / scale).max(axis=0)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_forward(dev, orc, seed):
+    from paper_2509_25347_amd import _lib, ops
+    rng = np.random.default_rng(1000 + seed)
+    case = random_case(rng)
+    N = case["N"]
+    K = int(rng.integers(1, 10))
+    opt = int(rng.integers(0, 3))
+    mapping = int(rng.choice([_lib.MAP_AUTO, _lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 8 else [])))
+    rg, rd, ts, v = to_dev(case, dev)
+    try:
+        _lib.set_mapping(N, mapping)
+        ops.clear_status()
+        out = ops.expm_apply(rg, rd, ts, v, case["dt"], k_max=K, option=opt)
+        status = ops.get_status()
+    finally:
+        _lib.set_mapping(N, _lib.MAP_AUTO)
+    got = out.cpu().numpy()
+    ref, kms, nrm, st = orc.apply_cells(case["rho_g"], case["rho_d"], case["t_stop"], case["v"],
+                                        case["dt"], K=K, option=opt)
+    label = (seed, N, case["C"], case["D"], case["dt"], K, opt, mapping)
+    assert status == st, label
+    assert np.array_equal(np.isnan(got), np.isnan(ref)), label
+    good = ~np.isnan(ref).any(axis=(0, 1))
+    if good.any():
+        e = cell_errors(got[..., good], ref[..., good], case["v"][..., good])
+        assert (e <= np.maximum(4 * U * nrm[good], 1e-13)).all(), (label, e.max())
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_rk1_and_variants(dev, orc, seed):
+    from paper_2509_25347_amd import _lib, ops
+    rng = np.random.default_rng(2000 + seed)
+    case = random_case(rng)
+    N = case["N"]
+    rg, rd, ts, v = to_dev(case, dev)
+    label = (seed, N, case["C"], case["D"], case["dt"])
+    # backward Euler
+    ops.clear_status()
+    out = ops.rk1_apply(rg, rd, ts, v, case["dt"])
+    status = ops.get_status()
+    ref, st = orc.rk1_cells(case["rho_g"], case["rho_d"], case["t_stop"], case["v"], case["dt"])
+    got = out.cpu().numpy()
+    assert status == st, label
+    assert np.array_equal(np.isnan(got), np.isnan(ref)), label
+    good = ~np.isnan(ref).any(axis=(0, 1))
+    if good.any():
+        e = cell_errors(got[..., good], ref[..., good], case["v"][..., good])
+        assert e.max() <= (4 * N + 16) * U, (label, e.max() / U)
+    # the bound test and the Pade step against the oracle's own versions
+    for gpu_opt, orc_opt in ((2 | _lib.OPTION_BOUND_TEST, 2 | orc.BOUND_TEST),
+                             (_lib.OPTION_PADE, orc.PADE)):
+        ops.clear_status()
+        out = ops.expm_apply(rg, rd, ts, v, case["dt"], option=gpu_opt)
+        status = ops.get_status()
+        ref, kms, nrm, st = orc.apply_cells(case["rho_g"], case["rho_d"], case["t_stop"],
+                                            case["v"], case["dt"], option=orc_opt)
+        got = out.cpu().numpy()
+        assert status == st, (label, gpu_opt)
+        assert np.array_equal(np.isnan(got), np.isnan(ref)), (label, gpu_opt)
+        if good.any():
+            e = cell_errors(got[..., good], ref[..., good], case["v"][..., good])
+            assert (e <= np.maximum(4 * U * nrm[good], 1e-13)).all(), (label, gpu_opt, e.max())
