@@ -38,7 +38,6 @@ def random_case(rng):
     m = rng.random((N, C))
     t_stop[m < 0.05] = np.inf
     rho_d[(m > 0.05) & (m < 0.1)] = 0.0
-    bad = []
     if C >= 5 and rng.random() < 0.5:
         cells = rng.choice(C, size=min(3, C), replace=False)
         kinds = rng.integers(0, 4, len(cells))
@@ -51,7 +50,6 @@ def random_case(rng):
                 v[rng.integers(D), rng.integers(N + 1), c] = np.nan
             else:
                 rho_d[rng.integers(N), c] = np.inf
-            bad.append(int(c))
     return dict(N=N, C=C, D=D, ld=ld, dt=dt, rho_g=rho_g, rho_d=rho_d, t_stop=t_stop, v=v)
 
 
@@ -136,3 +134,52 @@ def test_random_rk1_and_variants(dev, orc, seed):
         if good.any():
             e = cell_errors(got[..., good], ref[..., good], case["v"][..., good])
             assert (e <= np.maximum(4 * U * nrm[good], 1e-13)).all(), (label, gpu_opt, e.max())
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_batched_plan(dev, orc, seed):
+    """Random block tables (block sizes ragged against the 64-cell lane items,
+    8-cell MFMA items and 16-cell workgroups; every N; D = 1..3), K_AUTO or a
+    fixed cap, a pinned or tuned configuration: every block equals the plain
+    launch with the plan's cap and mapping bit for bit, and sampled blocks
+    meet the oracle's bar."""
+    from paper_2509_25347_amd import _lib, ops
+    from paper_2509_25347_amd import workloads as W
+    rng = np.random.default_rng(3000 + seed)
+    bc = int(rng.choice([1, 3, 17, 64, 65, 200]))
+    nb = int(rng.choice([1, 7, 33]))
+    D = int(rng.integers(1, 4))
+    k_req = int(rng.choice([_lib.K_AUTO, 9, 5]))
+    batch = W.make_batched(n_blocks=nb, block_cells=bc, D=D, seed_cfg=50 + seed)
+    plan = ops.BatchPlan(batch["n_species"], bc, D, batch["dt"], k_max=k_req)
+    fields, v = plan.pack(batch["blocks"], dev)
+    out = torch.empty_like(v)
+    if rng.random() < 0.5:
+        plan.autotune(fields, v, out)
+    else:
+        plan.set_config(int(rng.integers(4, 9)), str(rng.choice(["persistent", "grid", "per_n"])))
+    lmax, _ = plan.config()
+    ks = plan.k_max()
+    got = plan.apply(fields, v)
+    torch.cuda.synchronize()
+    label = (seed, bc, nb, D, k_req, plan.config())
+    try:
+        for N in range(1, 17):
+            _lib.set_mapping(N, _lib.MAP_LANE if N <= lmax else _lib.MAP_WAVE)
+        for b, blk in enumerate(batch["blocks"]):
+            N = blk["rho_d"].shape[0]
+            T = {k: torch.from_numpy(np.ascontiguousarray(blk[k])).to(dev)
+                 for k in ("rho_g", "rho_d", "t_stop", "v")}
+            ref = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], batch["dt"],
+                                 k_max=ks[N - 1])
+            g = plan.block_view(got, b)
+            assert torch.equal(g, ref), (label, b, N)
+            if b % 5 == 0:
+                o, kms, nrm, st = orc.apply_cells(blk["rho_g"], blk["rho_d"], blk["t_stop"],
+                                                  blk["v"], batch["dt"], K=ks[N - 1])
+                e = cell_errors(g.cpu().numpy(), o, blk["v"])
+                assert (e <= np.maximum(4 * U * nrm, 1e-13)).all(), (label, b)
+    finally:
+        for N in range(1, 17):
+            _lib.set_mapping(N, _lib.MAP_AUTO)
+        plan.close()
