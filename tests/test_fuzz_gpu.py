@@ -183,3 +183,54 @@ def test_random_batched_plan(dev, orc, seed):
         for N in range(1, 17):
             _lib.set_mapping(N, _lib.MAP_AUTO)
         plan.close()
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_adjoint(dev, orc, seed):
+    """Random fused forward + adjoint cases (N, C, D, dt over six decades,
+    K, option, mapping) against the oracle's reverse-mode gradient, with the
+    per-group bar of the dedicated adjoint tests (1e-9 of the group's scale
+    or of S = sum_c ||w_c|| ||v_c||)."""
+    from paper_2509_25347_amd import _lib, ops
+    rng = np.random.default_rng(4000 + seed)
+    N = int(rng.integers(1, 17))
+    C = int(rng.choice([1, 3, 17, 63, 65, 129, 300]))
+    D = int(rng.integers(1, 4))
+    dt = float(10.0 ** rng.uniform(-3, 3))
+    rho_g = rng.uniform(0.2, 5.0, C)
+    rho_d = 10.0 ** rng.uniform(-3, 0.5, (N, C)) * rho_g[None]
+    t_stop = 10.0 ** rng.uniform(-3, 2, (N, C))
+    v = rng.standard_normal((D, N + 1, C))
+    w = rng.standard_normal((D, N + 1, C))
+    K = int(rng.integers(5, 10))
+    opt = int(rng.integers(0, 3))
+    mapping = int(rng.choice([_lib.MAP_AUTO, _lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 8 else [])))
+    T = {k: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+         for k, x in (("rho_g", rho_g), ("rho_d", rho_d), ("t_stop", t_stop), ("v", v), ("w", w))}
+    try:
+        _lib.set_mapping(N, mapping)
+        res = ops.expm_apply_backward(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], T["w"], dt,
+                                      k_max=K, option=opt)
+        torch.cuda.synchronize()
+    finally:
+        _lib.set_mapping(N, _lib.MAP_AUTO)
+    v_out, g_v, g_logt, g_rho, g_rho_g = (x.cpu().numpy() for x in res)
+    rv, rgv, rlt, rrho, rrg, st = orc.grad_cells(rho_g, rho_d, t_stop, v, w, dt, K=K, option=opt)
+    assert st == 0
+    S = (np.abs(w).max(axis=1) * np.abs(v).max(axis=1)).sum(axis=0)
+    Sr = S / rho_g
+
+    def err(got, ref, floor=None):
+        g = np.moveaxis(got, -1, 0).reshape(C, -1)
+        r = np.moveaxis(ref, -1, 0).reshape(C, -1)
+        sc = np.abs(r).max(axis=1)
+        if floor is not None:
+            sc = np.maximum(sc, floor)
+        sc = np.where(sc == 0, 1.0, sc)
+        return np.abs(g - r).max(axis=1) / sc
+
+    label = (seed, N, C, D, dt, K, opt, mapping)
+    for name, e in (("v_out", err(v_out, rv)), ("g_v", err(g_v, rgv)),
+                    ("g_logt", err(g_logt, rlt, S)), ("g_rho_d", err(g_rho, rrho, Sr)),
+                    ("g_rho_g", np.abs(g_rho_g - rrg) / np.maximum(np.abs(rrg), Sr))):
+        assert np.isfinite(e).all() and e.max() <= 1e-9, (label, name, e.max())
