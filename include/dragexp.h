@@ -277,7 +277,7 @@ int drag_plan_autotune(drag_plan *plan, const double *fields,
 #define DRAG_MFMA_PER_N 2
 int drag_plan_config(const drag_plan *plan, int32_t *lane_max,
                      int32_t *mfma_mode);
-/* Pin a launch configuration instead of the tuned one: lane_max in 4..8 and
+/* Pin a launch configuration instead of the tuned one: lane_max in 4..12 and
  * an mfma_mode above (DRAG_ERR_OPTION otherwise, the plan unchanged).  The
  * next drag_expm_apply_batched re-captures; results do not depend on it. */
 int drag_plan_set_config(drag_plan *plan, int32_t lane_max, int32_t mfma_mode);
@@ -308,13 +308,16 @@ int drag_select(double norm, int32_t k_max, int32_t option, int32_t *k,
 /* ---- launch tuning ------------------------------------------------------------ */
 /* The per-N mapping used by drag_expm_apply, drag_expm_apply_backward and
  * the batched plan (for species count n_species, host-side, per process):
- *   DRAG_MAP_LANE  vector ALU, one cell per lane (N <= 8 only; the adjoint
- *                  at N = 8 runs one cell per pair of lanes);
+ *   DRAG_MAP_LANE  vector ALU: one cell per lane for N <= 8, one cell per
+ *                  pair of lanes for the forward at N = 9..12 (the adjoint:
+ *                  one lane to N = 7, a pair at 8, and the MFMA kernel
+ *                  above 8);
  *   DRAG_MAP_WAVE  FP64 MFMA: four cells per 64-lane wavefront, one
  *                  exponential at a time on 16 x 16 tiles (the adjoint for
  *                  N <= 8 on one tile holding the 2N x 2N block form);
- *   DRAG_MAP_AUTO  the measured default (lane for N <= 8, MFMA above).
- * DRAG_ERR_OPTION for an unknown mapping or LANE with N > 8.
+ *   DRAG_MAP_AUTO  the measured default (the forward: lane to N = 12, MFMA
+ *                  above; the adjoint: lane to N = 8).
+ * DRAG_ERR_OPTION for an unknown mapping or LANE with N > 12.
  * drag_get_mapping reports the forward's mapping. */
 #define DRAG_MAP_AUTO 0
 #define DRAG_MAP_LANE 1

@@ -21,6 +21,7 @@
 
 #include "common.hpp"
 #include "lane.hpp"
+#include "pair.hpp"
 #include "wave.hpp"
 
 namespace dragexp {
@@ -125,6 +126,20 @@ __global__ void __launch_bounds__(256) k_batched_lane(BatchArgs B) {
   const bool active = lane < it.count;
   const int64_t c = (int64_t)it.first + lane;
   lane_forward_cell<N>(A, c, active ? c : it.first, active);
+}
+
+// One 32-cell item per wavefront, two lanes per cell (N = 9..12).
+template <int N>
+__global__ void __launch_bounds__(256) k_batched_pair(BatchArgs B) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int idx = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
+  if (idx >= B.n_items) return;  // uniform over the wavefront
+  const BatchItem it = B.items[idx];
+  const CellArgs A = block_args(B, it);
+  const int p = lane >> 1;
+  const bool active = p < it.count;
+  const int64_t c = (int64_t)it.first + p;
+  pair_forward_cell<N>(A, c, active ? c : it.first, active, lane & 1);
 }
 
 }  // namespace dragexp

@@ -24,7 +24,8 @@
 
 namespace dragexp {
 
-constexpr int kLaneMaxN = 8;
+constexpr int kLaneMaxN = 8;   // one lane per cell
+constexpr int kPairMaxN = 12;  // two lanes per cell (forward)
 
 // ---- drag_build -------------------------------------------------------------
 struct BuildArgs {
@@ -134,6 +135,13 @@ static int launch_forward_big(const CellArgs& A, int N, hipStream_t st) {
   return hip_status(hipGetLastError());
 }
 
+template <int N>
+static int launch_forward_pair(const CellArgs& A, hipStream_t st) {
+  const Grid gr = grid_for((A.n_cells + 127) / 128);  // 128 cells per workgroup
+  hipLaunchKernelGGL(k_forward_pair<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  return hip_status(hipGetLastError());
+}
+
 using FwdFn = int (*)(const CellArgs&, hipStream_t);
 using BwdFn = int (*)(const BackArgs&, hipStream_t);
 
@@ -223,20 +231,26 @@ static FwdFn wave_fwd_method(int N) {
   return tab[N - 1];
 }
 
+// The vector-ALU forward: one lane per cell up to N = 8, a pair of lanes per
+// cell for N = 9..12.
 static FwdFn lane_fwd(int N) {
-  static const FwdFn tab[kLaneMaxN] = {
-      launch_forward_lane<1>, launch_forward_lane<2>, launch_forward_lane<3>,
-      launch_forward_lane<4>, launch_forward_lane<5>, launch_forward_lane<6>,
-      launch_forward_lane<7>, launch_forward_lane<8>};
+  static const FwdFn tab[kPairMaxN] = {
+      launch_forward_lane<1>,  launch_forward_lane<2>,  launch_forward_lane<3>,
+      launch_forward_lane<4>,  launch_forward_lane<5>,  launch_forward_lane<6>,
+      launch_forward_lane<7>,  launch_forward_lane<8>,  launch_forward_pair<9>,
+      launch_forward_pair<10>, launch_forward_pair<11>, launch_forward_pair<12>};
   return tab[N - 1];
 }
 
 // Tuned default mapping per N (index N - 1).  Overridable with
-// drag_set_mapping.
+// drag_set_mapping.  The vector ALU up to N = 12 (one lane per cell to 8, two
+// lanes per cell for 9..12: measured on MI355X over 2^18 cells, 2.0x faster
+// than the MFMA tile at N = 9, 10 and 1.1x at 11, 12, whose 16 x 16 tile is
+// mostly padding there), the MFMA kernel above.
 static int g_default_map[16] = {
     DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
     DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
-    DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
+    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
 static int g_map_override[16] = {0};
 
@@ -254,7 +268,7 @@ static int g_default_map_bwd[16] = {
 static int mapping_for(int N) {
   const int o = g_map_override[N - 1];
   int m = o ? o : g_default_map[N - 1];
-  if (m == DRAG_MAP_LANE && N > kLaneMaxN) m = DRAG_MAP_WAVE;
+  if (m == DRAG_MAP_LANE && N > kPairMaxN) m = DRAG_MAP_WAVE;
   return m;
 }
 
@@ -324,8 +338,8 @@ static bool overlap(Range a, Range b) {
 
 
 // ---- batched plans ----------------------------------------------------------------
-constexpr int kBatchVariants = 5;
-constexpr int kBatchLmax[kBatchVariants] = {4, 5, 6, 7, 8};
+constexpr int kBatchVariants = 9;
+constexpr int kBatchLmax[kBatchVariants] = {4, 5, 6, 7, 8, 9, 10, 11, 12};
 constexpr int kWaveItemCells = 8;
 // how the MFMA branch runs: a persistent grid over the item queue, a plain
 // grid over the blocks (N at run time), or one plain grid per N
@@ -345,8 +359,8 @@ struct BatchVariant {
   int n_wave_blocks = 0;
   BatchItem* d_wave_n[kMaxSpecies + 1] = {};  // the same blocks whole, per N
   int n_wave_n[kMaxSpecies + 1] = {};
-  BatchItem* d_lane[kLaneMaxN + 1] = {};  // 64-cell lane items per N <= lmax
-  int n_lane[kLaneMaxN + 1] = {};
+  BatchItem* d_lane[kPairMaxN + 1] = {};  // lane (64-cell) or pair (32-cell) items per N <= lmax
+  int n_lane[kPairMaxN + 1] = {};
 };
 
 template <int N>
@@ -379,6 +393,11 @@ static void batched_wave_n(int N, const BatchArgs& B, int gpb, hipStream_t st) {
   }
 }
 
+template <int N>
+static void launch_batched_pair(const BatchArgs& B, hipStream_t st) {
+  hipLaunchKernelGGL(k_batched_pair<N>, dim3((B.n_items + 3) / 4), dim3(256), 0, st, B);
+}
+
 static void batched_lane(int N, const BatchArgs& B, hipStream_t st) {
   switch (N) {
     case 1: launch_batched_lane<1>(B, st); break;
@@ -388,7 +407,11 @@ static void batched_lane(int N, const BatchArgs& B, hipStream_t st) {
     case 5: launch_batched_lane<5>(B, st); break;
     case 6: launch_batched_lane<6>(B, st); break;
     case 7: launch_batched_lane<7>(B, st); break;
-    default: launch_batched_lane<8>(B, st); break;
+    case 8: launch_batched_lane<8>(B, st); break;
+    case 9: launch_batched_pair<9>(B, st); break;
+    case 10: launch_batched_pair<10>(B, st); break;
+    case 11: launch_batched_pair<11>(B, st); break;
+    default: launch_batched_pair<12>(B, st); break;
   }
 }
 
@@ -489,7 +512,7 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
     BatchVariant& V = P->var[v];
     V.lmax = kBatchLmax[v];
     std::vector<BatchItem> wave, wave_blocks;
-    std::vector<BatchItem> lane[kLaneMaxN + 1], wave_n[kMaxSpecies + 1];
+    std::vector<BatchItem> lane[kPairMaxN + 1], wave_n[kMaxSpecies + 1];
     for (int b = 0; b < P->n_blocks; ++b) {
       const int n = P->n_species[b];
       const bool is_lane = n <= V.lmax;
@@ -497,7 +520,7 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
         wave_blocks.push_back(BatchItem{b, n, 0, P->block_cells});
         wave_n[n].push_back(BatchItem{b, n, 0, P->block_cells});
       }
-      const int step = is_lane ? 64 : kWaveItemCells;
+      const int step = is_lane ? (n <= kLaneMaxN ? 64 : 32) : kWaveItemCells;
       for (int first = 0; first < P->block_cells; first += step) {
         const BatchItem it{b, n, first, std::min(step, P->block_cells - first)};
         if (is_lane) lane[n].push_back(it);
@@ -508,7 +531,7 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
     V.n_wave_blocks = (int)wave_blocks.size();
     int rc = upload(&V.d_wave, wave);
     if (!rc) rc = upload(&V.d_wave_blocks, wave_blocks);
-    for (int n = 1; n <= kLaneMaxN && !rc; ++n) {
+    for (int n = 1; n <= kPairMaxN && !rc; ++n) {
       V.n_lane[n] = (int)lane[n].size();
       rc = upload(&V.d_lane[n], lane[n]);
     }
@@ -556,7 +579,7 @@ static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
   for (int n = 0; n <= kMaxSpecies; ++n) B.k_max_n[n] = P->k_n[n];
   if (hipEventRecord(P->ev_fork, main) != hipSuccess) return DRAG_ERR_HIP;
   if (hipStreamWaitEvent(side, P->ev_fork, 0) != hipSuccess) return DRAG_ERR_HIP;
-  for (int n = 1; n <= kLaneMaxN; ++n) {
+  for (int n = 1; n <= kPairMaxN; ++n) {
     if (V.n_lane[n] == 0) continue;
     BatchArgs L = B;
     L.items = V.d_lane[n];
@@ -1049,7 +1072,7 @@ int drag_set_mapping(int32_t n_species, int32_t mapping) {
   if (n_species < 1 || n_species > kMaxSpecies) return DRAG_ERR_N_SPECIES;
   if (mapping != DRAG_MAP_AUTO && mapping != DRAG_MAP_LANE && mapping != DRAG_MAP_WAVE)
     return DRAG_ERR_OPTION;
-  if (mapping == DRAG_MAP_LANE && n_species > kLaneMaxN) return DRAG_ERR_OPTION;
+  if (mapping == DRAG_MAP_LANE && n_species > kPairMaxN) return DRAG_ERR_OPTION;
   g_map_override[n_species - 1] = mapping;
   return DRAG_OK;
 }

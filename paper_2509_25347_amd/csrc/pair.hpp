@@ -346,4 +346,161 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
   }
 }
 
+// The forward with two lanes per cell, for the species counts where one lane
+// cannot hold Z and the squaring's product buffer (2 N^2 doubles) and the
+// 16 x 16 MFMA tile is mostly padding (N = 9, 10; valid for any N <= 10).
+// Same layout as the adjoint above: lane h holds rows h H .. h H + H - 1 in
+// the lane-relative column order.  Horner in the structured matrix,
+// F <- (F + c I) M with (F M)_ik = -F_ik b_k - (sum_l F_il) pb_k, is
+// row-local; each squaring W = Z (Z + 2I) fetches the partner's rows of Z
+// element by element (one DPP swap per dword, used for all H own rows); the
+// apply u = Z dv is row-local and e.u a pair sum.
+// The forward update of cell c by the pair of lanes (h = 0, 1) that share
+// it.  Both lanes of every pair of the wavefront must call it together (DPP
+// swaps, wavefront-wide maxima of m and s); a spare pair passes any valid
+// cell as cc, computes on it and stores nothing.
+template <int N>
+__device__ __forceinline__ void pair_forward_cell(const CellArgs& A, int64_t c, int64_t cc,
+                                                  bool active, int h) {
+  constexpr int H = (N + 1) / 2;
+  constexpr int W2 = 2 * H;
+  const int64_t ld = A.ld;
+  const int n1 = N + 1;
+  const int D = A.n_dim;
+  auto gcol = [&](int kappa) { return kappa < H ? h * H + kappa : (1 - h) * H + kappa - H; };
+
+  LaneCell<N> C;
+  lane_setup<N>(C, A.rho_g, A.rho_d, A.t_stop, ld, cc, A.dt, A.k_max, A.option);
+  bool vfin = true;
+  for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int j = 0; j <= N; ++j) vfin = vfin && isfinite(A.v_in[(int64_t)(d * n1 + j) * ld + cc]);
+  }
+  if (!vfin && !C.bad) C.bad = kBadVelocity;
+  const int s = C.kms.s, m = C.kms.m;
+
+  // scaled coefficients and e in the lane-relative column order
+  double nb[W2], npb[W2], er[H];
+#pragma unroll
+  for (int kap = 0; kap < W2; ++kap) {
+    const int g = gcol(kap);
+    double a = 0.0, p = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {  // select by value: no private-array indexing
+      a = (g == k) ? C.a[k] : a;
+      p = (g == k) ? C.p[k] : p;
+    }
+    nb[kap] = -ldexp(a, -s);
+    npb[kap] = -ldexp(p, -s);
+  }
+#pragma unroll
+  for (int r = 0; r < H; ++r) {
+    double e = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) e = (h * H + r == k) ? C.e[k] : e;
+    er[r] = e;
+  }
+
+  // Horner: Z = T_m(M) - I, own rows only
+  double Z[H][W2];
+#pragma unroll
+  for (int r = 0; r < H; ++r)
+#pragma unroll
+    for (int k = 0; k < W2; ++k) Z[r][k] = 0.0;
+  const int m_max = wave_max_int(m);
+  for (int it = m_max; it >= 1; --it) {
+    const double cf = (it <= m) ? kInvFact[it] : 0.0;
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      if (h * H + r < N) Z[r][r] += cf;  // own row r = relative column r
+      double rs = 0.0;
+#pragma unroll
+      for (int k = 0; k < W2; ++k) rs += Z[r][k];
+#pragma unroll
+      for (int k = 0; k < W2; ++k) Z[r][k] = fma(Z[r][k], nb[k], rs * npb[k]);
+    }
+  }
+
+  // squarings Z <- Z (Z + 2I); the partner's rows by DPP, columns half-rotated
+  const int s_max = wave_max_int(s);
+  for (int it = 0; it < s_max; ++it) {
+    double T[H][W2];
+#pragma unroll
+    for (int r = 0; r < H; ++r)
+#pragma unroll
+      for (int k = 0; k < W2; ++k) T[r][k] = 0.0;
+    // own rows of the right factor: relative column l of my rows is my row l
+#pragma unroll
+    for (int l = 0; l < H; ++l) {
+#pragma unroll
+      for (int k = 0; k < W2; ++k) {
+        const double b = Z[l][k] + ((k == l) ? 2.0 : 0.0);
+#pragma unroll
+        for (int r = 0; r < H; ++r) T[r][k] = fma(Z[r][l], b, T[r][k]);
+      }
+    }
+    // the partner's rows: its row l is my relative column H + l
+#pragma unroll
+    for (int l = 0; l < H; ++l) {
+#pragma unroll
+      for (int k = 0; k < W2; ++k) {
+        const double b = pair_swap(Z[l][(k + H) % W2]) + ((k == H + l) ? 2.0 : 0.0);
+#pragma unroll
+        for (int r = 0; r < H; ++r) T[r][k] = fma(Z[r][H + l], b, T[r][k]);
+      }
+    }
+    if (it < s) {
+#pragma unroll
+      for (int r = 0; r < H; ++r)
+#pragma unroll
+        for (int k = 0; k < W2; ++k) Z[r][k] = T[r][k];
+    }
+  }
+
+  // apply: u = Z dv for the own rows, e.u summed over the pair
+  const double qnan = __builtin_nan("");
+  for (int d = 0; d < D; ++d) {
+    const int64_t base = (int64_t)(d * n1) * ld;
+    const double v0 = A.v_in[base + cc];
+    double dv[W2];
+#pragma unroll
+    for (int k = 0; k < W2; ++k) {
+      const int g = gcol(k);  // a run-time row index is fine for memory
+      dv[k] = g < N ? A.v_in[base + (int64_t)(1 + g) * ld + cc] - v0 : 0.0;
+    }
+    double u[H], eu_own = 0.0;
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < W2; ++k) acc = fma(Z[r][k], dv[k], acc);
+      u[r] = acc;
+      eu_own = fma(er[r], acc, eu_own);
+    }
+    const double d0 = -pair_sum(eu_own, h) / C.sigma;
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        const int k = h * H + r;
+        if (k < N) {
+          const int64_t idx = base + (int64_t)(1 + k) * ld + c;
+          A.v_out[idx] = C.bad ? qnan : A.v_in[idx] + (d0 + u[r]);
+        }
+      }
+      if (h == 0) A.v_out[base + c] = C.bad ? qnan : v0 + d0;
+    }
+  }
+  if (C.bad && active && h == 0) atomicOr(&g_status_word, C.bad);
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_forward_pair(CellArgs A, int xcd_blocks) {
+  constexpr int kCells = 128;  // cells per workgroup, two lanes each
+  const int bid = blockIdx.x;
+  const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
+  const int64_t c = logical * kCells + (threadIdx.x >> 1);
+  const bool active = c < A.n_cells;
+  pair_forward_cell<N>(A, c, active ? c : 0, active, threadIdx.x & 1);
+}
+
 }  // namespace dragexp

@@ -152,8 +152,11 @@ def test_mapping_controls(L):
     _lib.set_mapping(3, _lib.MAP_WAVE)
     assert _lib.get_mapping(3) == _lib.MAP_WAVE
     _lib.set_mapping(3, _lib.MAP_AUTO)
+    _lib.set_mapping(12, _lib.MAP_LANE)  # the forward's pair of lanes goes to 12
+    assert _lib.get_mapping(12) == _lib.MAP_LANE
+    _lib.set_mapping(12, _lib.MAP_AUTO)
     with pytest.raises(_lib.DragError):
-        _lib.set_mapping(12, _lib.MAP_LANE)
+        _lib.set_mapping(13, _lib.MAP_LANE)
     with pytest.raises(_lib.DragError):
         _lib.set_mapping(0, _lib.MAP_WAVE)
 

@@ -77,14 +77,14 @@ def test_autotune_and_every_variant_result(ops, dev):
     fields, v = plan.pack(batch["blocks"], dev)
     out = torch.empty_like(v)
     lm = plan.autotune(fields, v, out)
-    assert 4 <= lm <= 8
+    assert 4 <= lm <= 12
     assert plan.config()[1] in ("persistent", "grid", "per_n")
     out2 = plan.apply(fields, v)
     torch.cuda.synchronize()
     refs = {lm: plain_per_block(ops, batch, dev, lane_max=lm)}
     for b in range(len(batch["blocks"])):
         assert np.array_equal(plan.block_view(out2, b).cpu().numpy(), refs[lm][b]), b
-    for lmax in range(4, 9):
+    for lmax in range(4, 13):
         if lmax not in refs:
             refs[lmax] = plain_per_block(ops, batch, dev, lane_max=lmax)
         for mode in ("persistent", "grid", "per_n"):

@@ -157,7 +157,7 @@ def test_random_batched_plan(dev, orc, seed):
     if rng.random() < 0.5:
         plan.autotune(fields, v, out)
     else:
-        plan.set_config(int(rng.integers(4, 9)), str(rng.choice(["persistent", "grid", "per_n"])))
+        plan.set_config(int(rng.integers(4, 13)), str(rng.choice(["persistent", "grid", "per_n"])))
     lmax, _ = plan.config()
     ks = plan.k_max()
     got = plan.apply(fields, v)

@@ -412,6 +412,40 @@ def test_wave_short_quads_and_ld(ops, dev, orc, N):
         _lib.set_mapping(N, _lib.MAP_AUTO)
 
 
+@pytest.mark.parametrize("N", [9, 10, 11, 12])
+def test_pair_forward_edges(ops, dev, orc, N):
+    """The two-lanes-per-cell forward (N = 9..12): cell counts cut against the
+    128-cell workgroup, leading-dimension padding, in place, bad cells next to
+    good ones, and the MFMA kernel's result within the oracle's bar."""
+    from paper_2509_25347_amd import _lib
+    assert _lib.get_mapping(N) == _lib.MAP_LANE
+    for C in (1, 2, 127, 129, 300):
+        d = W.make_stiff(N, C)
+        ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"])
+        got = run(ops, d, dev)
+        assert_parity(got, ref, nrm, d, f"pair N={N} C={C}")
+        ld = C + 3
+        big = {k: np.full(d[k].shape[:-1] + (ld,), np.nan) for k in ("rho_d", "t_stop", "v")}
+        for k in big:
+            big[k][..., :C] = d[k]
+        Tb = {k: torch.from_numpy(big[k]).to(dev)[..., :C] for k in big}
+        vv = torch.from_numpy(big["v"].copy()).to(dev)[..., :C]  # same padded layout
+        ops.expm_apply(torch.from_numpy(d["rho_g"]).to(dev), Tb["rho_d"], Tb["t_stop"], vv,
+                       d["dt"], out=vv)
+        torch.cuda.synchronize()
+        assert_parity(vv.cpu().numpy(), ref, nrm, d, f"pair N={N} C={C} ld in place")
+    d = W.make_jittered(N, 64)
+    rg, ts, v = d["rho_g"].copy(), d["t_stop"].copy(), d["v"].copy()
+    rg[2] = -1.0
+    ts[N - 1, 3] = 0.0
+    v[1, N, 5] = np.nan
+    ref, kms, nrm, st = orc.apply_cells(rg, d["rho_d"], ts, v, 1.0)
+    ops.clear_status()
+    got = run(ops, dict(rho_g=rg, rho_d=d["rho_d"], t_stop=ts, v=v, dt=1.0), dev)
+    assert ops.get_status() == st
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+
+
 def test_wave_bad_cells_inside_quads(ops, dev, orc):
     """Bad cells next to good ones in the same quad of the N = 16 kernel."""
     d = W.make("n16_stiff_3d", 64)
