@@ -326,8 +326,8 @@ int drag_select(double norm, int32_t k_max, int32_t option, int32_t *k,
  * per process).  Every K gives an approximant accurate to u (Alg. 1 keeps
  * ||dt K / 2^s||_1 <= theta_m); K trades polynomial degree against
  * squarings.  The defaults were measured on MI355X (2^18 cells per N): K = 3
- * or 4 for N <= 4, 5 for N = 5-6, 6 for N = 7-8 (0.72-0.98 of the time at
- * K = 9 on the one-lane kernel), 7 for N >= 9.  drag_set_k_max(N, 0)
+ * or 4 for N <= 4, 5 for N = 5-6, 6 for N = 7-12 (0.72-0.99 of the time at
+ * K = 9 on the vector-ALU kernels), 7 for N >= 13 (the MFMA kernel).  drag_set_k_max(N, 0)
  * restores the default; DRAG_ERR_N_SPECIES / DRAG_ERR_K_MAX otherwise. */
 int drag_set_k_max(int32_t n_species, int32_t k_max);
 int drag_get_k_max(int32_t n_species, int32_t *k_max);

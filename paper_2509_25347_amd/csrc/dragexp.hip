@@ -287,9 +287,10 @@ static int mapping_for_bwd(int N) {
 // squares densely (O(N^3)), so small N prefers low degrees; the MFMA kernel
 // is flat for K >= 7.  Measured on MI355X over 2^18 cells per N (stiff and
 // jittered recipes), the fastest K against K = 9: N = 2-4 K = 3-4 (0.72-0.86
-// of the time), N = 5-6 K = 5 (0.83-0.92), N = 7-8 K = 6 (0.88-0.98),
-// N >= 9 K = 7 (0.98-0.99).
-static const int g_default_kmax[16] = {4, 3, 3, 4, 5, 5, 6, 6, 7, 7, 7, 7, 7, 7, 7, 7};
+// of the time), N = 5-6 K = 5 (0.83-0.92), N = 7-8 K = 6 (0.88-0.98), and
+// on the two-lanes-per-cell kernel N = 9-12 K = 5-6 (0.88-0.99); the MFMA
+// kernel (N >= 13) K = 7 (0.98-0.99).
+static const int g_default_kmax[16] = {4, 3, 3, 4, 5, 5, 6, 6, 6, 6, 6, 6, 7, 7, 7, 7};
 static int g_kmax_override[16] = {0};
 
 static int k_for(int k_max, int N) {
