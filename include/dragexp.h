@@ -310,13 +310,13 @@ int drag_select(double norm, int32_t k_max, int32_t option, int32_t *k,
  * the batched plan (for species count n_species, host-side, per process):
  *   DRAG_MAP_LANE  vector ALU: one cell per lane for N <= 8, one cell per
  *                  pair of lanes for the forward at N = 9..12 (the adjoint:
- *                  one lane to N = 7, a pair at 8, and the MFMA kernel
- *                  above 8);
+ *                  one lane to N = 7, a pair at 8..10, and the MFMA kernel
+ *                  above 10);
  *   DRAG_MAP_WAVE  FP64 MFMA: four cells per 64-lane wavefront, one
  *                  exponential at a time on 16 x 16 tiles (the adjoint for
  *                  N <= 8 on one tile holding the 2N x 2N block form);
  *   DRAG_MAP_AUTO  the measured default (the forward: lane to N = 12, MFMA
- *                  above; the adjoint: lane to N = 8).
+ *                  above; the adjoint: lane to N = 10).
  * DRAG_ERR_OPTION for an unknown mapping or LANE with N > 12.
  * drag_get_mapping reports the forward's mapping. */
 #define DRAG_MAP_AUTO 0

@@ -26,6 +26,7 @@ namespace dragexp {
 
 constexpr int kLaneMaxN = 8;   // one lane per cell
 constexpr int kPairMaxN = 12;  // two lanes per cell (forward)
+constexpr int kPairBwdMaxN = 10;  // two lanes per cell (adjoint)
 
 // ---- drag_build -------------------------------------------------------------
 struct BuildArgs {
@@ -187,10 +188,11 @@ static BwdFn wave_bwd(int N) {
 }
 
 static BwdFn lane_bwd(int N) {
-  static const BwdFn tab[kLaneMaxN] = {
+  static const BwdFn tab[kPairBwdMaxN] = {
       launch_backward_lane<1>, launch_backward_lane<2>, launch_backward_lane<3>,
       launch_backward_lane<4>, launch_backward_lane<5>, launch_backward_lane<6>,
-      launch_backward_lane<7>, launch_backward_pair<8>};
+      launch_backward_lane<7>, launch_backward_pair<8>, launch_backward_pair<9>,
+      launch_backward_pair<10>};
   return tab[N - 1];
 }
 
@@ -256,13 +258,15 @@ static int g_map_override[16] = {0};
 
 // Default mapping of the adjoint.  The lane mapping keeps Y, dY and a
 // product buffer per cell in registers: one lane per cell up to N = 7, two
-// lanes per cell at N = 8, where one lane spills (pair.hpp).  Measured on
+// lanes per cell at N = 8..10, where one lane spills (pair.hpp).  Measured on
 // MI355X (2^18 stiff cells): N = 8 one lane 1.64 ms, two lanes 0.77 ms, MFMA
-// block form 1.08 ms; N = 7 one lane 0.54 ms, MFMA 1.07 ms.
+// block form 1.08 ms; N = 7 one lane 0.54 ms, MFMA 1.07 ms; N = 9, 10 two
+// lanes 1.51 / 1.56 ms against 2.83 / 2.84 for the MFMA kernel (1.5x on the
+// jittered cells).
 static int g_default_map_bwd[16] = {
     DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
     DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_LANE,
-    DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
+    DRAG_MAP_LANE, DRAG_MAP_LANE, DRAG_MAP_WAVE, DRAG_MAP_WAVE,
     DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE, DRAG_MAP_WAVE};
 
 static int mapping_for(int N) {
@@ -275,7 +279,7 @@ static int mapping_for(int N) {
 static int mapping_for_bwd(int N) {
   const int o = g_map_override[N - 1];
   int m = o ? o : g_default_map_bwd[N - 1];
-  if (m == DRAG_MAP_LANE && N > kLaneMaxN) m = DRAG_MAP_WAVE;
+  if (m == DRAG_MAP_LANE && N > kPairBwdMaxN) m = DRAG_MAP_WAVE;
   return m;
 }
 

@@ -1,5 +1,5 @@
-// pair.hpp -- the fused forward + adjoint with two lanes per cell (used at
-// N = 8; valid for any N <= 8).
+// pair.hpp -- two lanes per cell: the fused forward + adjoint (used at
+// N = 8..10) and the forward (N = 9..12).
 //
 // The one-lane adjoint keeps Y, dY and a product buffer (3 N^2 doubles) in
 // one lane: at N = 8 that exceeds the register file and spills.  Here the two

@@ -98,7 +98,7 @@ def test_backward_vs_oracle(ops, dev, orc, name, cells):
 def test_backward_every_n_both_mappings(ops, dev, orc, N):
     from paper_2509_25347_amd import _lib
     d = _weights(W.make_stiff(N, 301) if N % 2 == 0 else W.make_jittered(N, 301), seed=N)
-    maps = [_lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 8 else [])
+    maps = [_lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 10 else [])
     try:
         for mp in maps:
             _lib.set_mapping(N, mp)
@@ -124,6 +124,7 @@ FD_CASES = {
     "n3_lane": (lambda: W.make_jittered(3, 5), 3, 1),
     "n8_mfma_block": (lambda: W.make("n8_adjoint_3d", 6), 8, 2),
     "n12_mfma": (lambda: W.make_stiff(12, 5), 12, 2),
+    "n10_pair": (lambda: W.make_jittered(10, 5), 10, 1),
 }
 
 
@@ -134,8 +135,8 @@ def test_backward_vs_finite_differences(ops, dev, case):
     rho_i (the scale of e_i = rho_i / rho_g; a step relative to a small rho_i
     would divide the forward's rounding noise by a tiny number) and relative
     in rho_g.  Agreement to 1e-7 of the group scale.  One case per adjoint
-    kernel: one lane per cell, two lanes per cell (the N = 8 default), the
-    MFMA block form and the MFMA kernel for N >= 9."""
+    kernel: one lane per cell, two lanes per cell (the N = 8 default, and
+    N = 10), the MFMA block form and the MFMA kernel for N > 10."""
     from paper_2509_25347_amd import _lib
     make, n_map, mapping = FD_CASES[case]
     if n_map is not None:

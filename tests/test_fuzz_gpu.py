@@ -79,7 +79,7 @@ def test_random_forward(dev, orc, seed):
     N = case["N"]
     K = int(rng.integers(1, 10))
     opt = int(rng.integers(0, 3))
-    mapping = int(rng.choice([_lib.MAP_AUTO, _lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 8 else [])))
+    mapping = int(rng.choice([_lib.MAP_AUTO, _lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 12 else [])))
     rg, rd, ts, v = to_dev(case, dev)
     try:
         _lib.set_mapping(N, mapping)
@@ -204,7 +204,7 @@ def test_random_adjoint(dev, orc, seed):
     w = rng.standard_normal((D, N + 1, C))
     K = int(rng.integers(5, 10))
     opt = int(rng.integers(0, 3))
-    mapping = int(rng.choice([_lib.MAP_AUTO, _lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 8 else [])))
+    mapping = int(rng.choice([_lib.MAP_AUTO, _lib.MAP_WAVE] + ([_lib.MAP_LANE] if N <= 12 else [])))
     T = {k: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
          for k, x in (("rho_g", rho_g), ("rho_d", rho_d), ("t_stop", t_stop), ("v", v), ("w", w))}
     try:
