@@ -24,7 +24,7 @@
  * with N = n_species in [1, 16] and D = n_dim in [1, 3]; the D components
  * share one matrix K.  drag_build, drag_expm_apply and drag_expm_steps also
  * take N = 17..32 (a large-N kernel: one cell per wavefront on 2 x 2 blocks
- * of MFMA tiles, the plain Taylor step, K_AUTO = 9; built for cases such as
+ * of MFMA tiles, the plain Taylor step, K_AUTO = 7; built for cases such as
  * the paper's 20-species Collisions test, not tuned); the other calls
  * return DRAG_ERR_N_SPECIES above 16.
  *

@@ -299,7 +299,7 @@ static int g_kmax_override[16] = {0};
 
 static int k_for(int k_max, int N) {
   if (k_max != DRAG_K_AUTO) return k_max;
-  if (N > kMaxSpecies) return 9;  // the large-N kernel: not tuned
+  if (N > kMaxSpecies) return 7;  // the large-N kernel: K = 6-7 within 3 % (N = 17..32)
   const int o = g_kmax_override[N - 1];
   return o ? o : g_default_kmax[N - 1];
 }

@@ -306,7 +306,11 @@ def test_large_n_forward(ops, dev, orc, N):
         assert momentum_errors(g, d).max() <= 1e-12
         auto = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"],
                               k_max=_lib.K_AUTO)
-        assert torch.equal(auto, got)  # K_AUTO is 9 above 16 species
+        seven = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"], k_max=7)
+        assert torch.equal(auto, seven)  # K_AUTO is 7 above 16 species
+        ref7, _, nrm7, _ = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"],
+                                           K=7)
+        assert_parity(auto.cpu().numpy(), ref7, nrm7, d, f"N={N} K=7")
     d = W.make_stiff(N, 40)
     rg, ts, v = d["rho_g"].copy(), d["t_stop"].copy(), d["v"].copy()
     rg[3] = 0.0
