@@ -144,6 +144,10 @@ def main():
     ap.add_argument("--rk1", action="store_true",
                     help="time the backward Euler step (drag_rk1_apply) on the workload instead "
                          "of the exponential, with its HBM roofline")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time per cell of the exponential (K = 9 and the tuned cap) and of the "
+                         "backward Euler step for N = 1..16 on 64^3 cells (the paper's Fig. 6 "
+                         "axes); one JSON object")
     ap.add_argument("--report", action="store_true",
                     help="every workload configuration: GPU rate, roofline fractions, and the "
                          "oracle beside it (1-core and all-core rates, errors on the same "
@@ -176,6 +180,9 @@ def main():
     name = args.workload
     if args.report:
         print(json.dumps(config_report(torch, ops, _lib, workloads, dev)), flush=True)
+        return
+    if args.sweep:
+        print(json.dumps(n_sweep(torch, ops, _lib, workloads, dev)), flush=True)
         return
     if args.adjoint:
         print(json.dumps(adjoint_only(torch, ops, _lib, workloads, dev, name, args)), flush=True)
@@ -278,6 +285,28 @@ def _time(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def _graph_time(torch, fn, launches=20, replays=20):
+    """Device time per launch with the host out of the loop: `launches`
+    calls captured into one HIP graph (torch.cuda.graph on its capture
+    stream, which the library launches on) and replayed; ms per launch."""
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(launches):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(replays):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / (replays * launches)
+
+
 def _oracle_rates(d, sample, threads):
     """Oracle (CPU leg) on the first `sample` cells: its outputs, the
     single-thread rate, and the rate with `threads` threads over chunks (the
@@ -338,6 +367,10 @@ def config_report(torch, ops, _lib, workloads, dev):
                "err_vs_oracle": _err_stats(got[..., :ref.shape[-1]], ref, d["v"][..., :ref.shape[-1]]),
                "oracle_sample": int(ref.shape[-1]), "oracle_1core_cells_per_s": r1,
                "oracle_all_cores_cells_per_s": rp}
+        if cfg == 1:  # launch-bound: the device time per launch, from graph replays
+            row["graph_replay_us_per_launch"] = 1e3 * _graph_time(
+                torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                              d["dt"], out=o))
         ms_auto = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
                                                       d["dt"], k_max=_lib.K_AUTO, out=o), 50, 5)
         row["taylor_cap_tuned"] = {"k_max": _lib.get_k_max(N), "ms": ms_auto,
@@ -418,6 +451,30 @@ def adjoint_only(torch, ops, _lib, workloads, dev, name, args):
             "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": name, "n_cells": C, "n_species": N}}
+
+
+def n_sweep(torch, ops, _lib, workloads, dev, cells=1 << 18):
+    """Time per cell against the species count, as the paper plots it (Fig. 6:
+    EXP and RK1 on 64^3 cells): stiff and jittered synthetic cells (the
+    Dustywave stopping times are not available), D = 3, the default mapping."""
+    out = {"cells": cells, "rows": []}
+    for recipe, make in (("stiff", workloads.make_stiff), ("jittered", workloads.make_jittered)):
+        for N in range(1, 17):
+            d = make(N, cells)
+            T = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev)
+                 for k in ("rho_g", "rho_d", "t_stop", "v")}
+            o = torch.empty_like(T["v"])
+            t9 = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                     d["dt"], out=o), 20, 3)
+            ta = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                     d["dt"], k_max=_lib.K_AUTO, out=o), 20, 3)
+            tr = _time(torch, lambda: ops.rk1_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
+                                                    d["dt"], out=o), 20, 3)
+            out["rows"].append({"recipe": recipe, "N": N, "exp_k9_s_per_cell": t9 * 1e-3 / cells,
+                                "exp_auto_s_per_cell": ta * 1e-3 / cells,
+                                "rk1_s_per_cell": tr * 1e-3 / cells, "k_auto": _lib.get_k_max(N),
+                                "exp_over_rk1": min(t9, ta) / tr})
+    return out
 
 
 def rk1_roofline(ms, C, N, D, workload):
