@@ -501,3 +501,36 @@ def test_many_steps_against_exact(ops, dev, name):
                          ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"]),
                          d["dt"]).cpu().numpy()
     assert cell_errors(one, two, d["v"]).max() <= 2e-13
+
+
+def test_plain_launches_captured_in_a_graph(ops, dev):
+    """drag_expm_apply and drag_rk1_apply captured into one HIP graph (torch's
+    capture stream, which the library launches on) and replayed several
+    times with other GPU work in between: every replay equals the eager
+    result bit for bit (the calls enqueue no memset or allocation)."""
+    d4 = W.make("n4_3d", 5000)
+    d16 = W.make("n16_stiff_3d", 2000)
+    T4, T16 = _to(d4, dev), _to(d16, dev)
+    o4, o16, r4 = (torch.empty_like(x["v"]) for x in (T4, T16, T4))
+
+    def work():
+        ops.expm_apply(T4["rho_g"], T4["rho_d"], T4["t_stop"], T4["v"], d4["dt"], out=o4)
+        ops.expm_apply(T16["rho_g"], T16["rho_d"], T16["t_stop"], T16["v"], d16["dt"], out=o16)
+        ops.rk1_apply(T4["rho_g"], T4["rho_d"], T4["t_stop"], T4["v"], d4["dt"], out=r4)
+
+    work()
+    torch.cuda.synchronize()
+    ref = [x.clone() for x in (o4, o16, r4)]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        work()
+    junk = torch.randn(1 << 20, dtype=torch.float64, device=dev)
+    for rep in range(4):
+        for x in (o4, o16, r4):
+            x.fill_(float("nan"))
+        junk = junk * 1.5 + 1.0
+        ops.expm_apply(T4["rho_g"], T4["rho_d"], T4["t_stop"], T4["v"], 2.0)
+        g.replay()
+        torch.cuda.synchronize()
+        for x, y in zip((o4, o16, r4), ref):
+            assert torch.equal(x, y), rep
