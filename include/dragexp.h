@@ -307,7 +307,9 @@ int drag_select(double norm, int32_t k_max, int32_t option, int32_t *k,
 
 /* ---- launch tuning ------------------------------------------------------------ */
 /* The per-N mapping used by drag_expm_apply, drag_expm_apply_backward and
- * the batched plan (for species count n_species, host-side, per process):
+ * the batched plan (for species count n_species, host-side, per process; the
+ * setters, like drag_set_k_max, are not synchronised: set them before
+ * launching from several host threads):
  *   DRAG_MAP_LANE  vector ALU: one cell per lane for N <= 8, one cell per
  *                  pair of lanes for the forward at N = 9..12 (the adjoint:
  *                  one lane to N = 7, a pair at 8..10, and the MFMA kernel
