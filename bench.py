@@ -258,16 +258,24 @@ def main():
         "roofline": roof,
         "wall_s_timed": wall,
     }
+    # the side measurements each report an error in place rather than lose
+    # the line (the headline above is complete by now)
+    def side(key, fn):
+        try:
+            res[key] = fn()
+        except Exception as e:  # noqa: BLE001
+            res[key] = {"error": f"{type(e).__name__}: {e}"}
+
     if not args.no_comparisons:
-        res["fwd_bwd_vs_fwd"] = adjoint_measurement(torch, ops, workloads, dev)
-        res["batched_vs_plain"] = batched_measurement(torch, ops, workloads, dev)
-        res["rk1_vs_expm"] = rk1_measurement(torch, ops, workloads, dev)
-        res["bound_test"] = bound_test_measurement(torch, ops, _lib, workloads, dev)
-        res["pade_vs_taylor"] = pade_measurement(torch, ops, _lib, workloads, dev)
+        side("fwd_bwd_vs_fwd", lambda: adjoint_measurement(torch, ops, workloads, dev))
+        side("batched_vs_plain", lambda: batched_measurement(torch, ops, workloads, dev))
+        side("rk1_vs_expm", lambda: rk1_measurement(torch, ops, workloads, dev))
+        side("bound_test", lambda: bound_test_measurement(torch, ops, _lib, workloads, dev))
+        side("pade_vs_taylor", lambda: pade_measurement(torch, ops, _lib, workloads, dev))
     if args.extra:
-        res["extra"] = extra_measurements(torch, ops, workloads, dev)
+        side("extra", lambda: extra_measurements(torch, ops, workloads, dev))
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(d)
+        side("cpu_baseline", lambda: cpu_baseline(d))
     print(json.dumps(res), flush=True)
 
 
