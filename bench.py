@@ -74,7 +74,21 @@ def algorithmic_bytes(C, N, D):
 
 KERNEL_SOURCES = {"k_forward_wave": ("common.hpp", "wave.hpp"),
                   "k_forward_lane": ("common.hpp", "lane.hpp"),
+                  "k_forward_lane_stream": ("common.hpp", "lane.hpp"),
+                  "k_forward_pair": ("common.hpp", "lane.hpp", "pair.hpp"),
+                  "k_forward_big": ("common.hpp", "wave.hpp", "big.hpp"),
                   "k_rk1_lane": ("common.hpp", "rk1.hpp")}
+
+
+def forward_kernel(N, mapping, n_cells):
+    """The kernel drag_expm_apply launches for N species under `mapping`."""
+    if mapping == "wave":
+        return "k_forward_wave" if N <= 16 else "k_forward_big"
+    if N <= 4:
+        return "k_forward_lane"
+    if N <= 8:
+        return "k_forward_lane_stream" if n_cells <= 1 << 29 else "k_forward_lane"
+    return "k_forward_pair"
 
 
 def source_hash(kernel):
@@ -230,8 +244,8 @@ def main():
         "peak": FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved_tflops / FP64_PEAK_TFLOPS, 4),
-        "traffic": profiled_traffic(f"k_forward_{mapping}", name),
-        "kernel": f"k_forward_{mapping}<{N}>",
+        "traffic": profiled_traffic(forward_kernel(N, mapping, C), name),
+        "kernel": f"{forward_kernel(N, mapping, C)}<{N}>",
         "flops_per_launch": f_alg,
         "executed_flops_per_launch": f_exe,
         "executed_frac": round(f_exe / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "../../include/dragexp.h"
@@ -107,8 +108,53 @@ static Grid grid_for(int64_t n_units) {
 
 static int hip_status(hipError_t e) { return e == hipSuccess ? DRAG_OK : DRAG_ERR_HIP; }
 
+// Compute units per device id (0 until asked).
+static std::atomic<int> g_device_cus[64];
+
+// Workgroups of 256 threads of `kernel` resident on the current device at
+// once (`per_cu`, the kernel's occupancy, is cached by the caller).
+static int resident_blocks(const void* kernel, std::atomic<int>& per_cu, int* out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DRAG_ERR_HIP;
+  int cus = g_device_cus[dev].load(std::memory_order_relaxed);
+  if (cus == 0) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return DRAG_ERR_HIP;
+    g_device_cus[dev].store(cus, std::memory_order_relaxed);
+  }
+  int pc = per_cu.load(std::memory_order_relaxed);
+  if (pc == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kernel, 256, 0) != hipSuccess)
+      return DRAG_ERR_HIP;
+    if (pc < 1) pc = 1;
+    per_cu.store(pc, std::memory_order_relaxed);
+  }
+  *out = pc * cus;
+  return DRAG_OK;
+}
+
+// The one-lane forward: the streaming kernel (prefetch of the next cell,
+// a grid of the resident wavefronts) for N = 5..8, where each wavefront
+// holds many registers and few fit on a SIMD, and the one-shot kernel for
+// N <= 4, where enough wavefronts are resident to hide the loads and the
+// extra registers of the prefetch would halve them (measured, 2^20 cells).
+constexpr int kLaneStreamMinN = 5;
+
 template <int N>
 static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
+  if constexpr (N >= kLaneStreamMinN) {
+    if (A.n_cells <= (int64_t(1) << 29)) {  // 32-bit lane byte offsets
+      static std::atomic<int> per_cu{0};
+      int resident = 0;
+      const int rc = resident_blocks(reinterpret_cast<const void*>(&k_forward_lane_stream<N>),
+                                     per_cu, &resident);
+      if (rc) return rc;
+      const int64_t need = (A.n_cells + 255) / 256;
+      const unsigned blocks = (unsigned)(need < resident ? (need < 1 ? 1 : need) : resident);
+      hipLaunchKernelGGL(k_forward_lane_stream<N>, dim3(blocks), dim3(256), 0, st, A);
+      return hip_status(hipGetLastError());
+    }
+  }
   const Grid gr = grid_for((A.n_cells + 255) / 256);
   hipLaunchKernelGGL(k_forward_lane<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
   return hip_status(hipGetLastError());

@@ -94,25 +94,11 @@ struct LaneCell {
   Kms kms;
 };
 
+// The rest of the set-up once the coefficients are in C: ||A||_1 (the gas
+// column |A00| + a_1 + .. + a_N, the species columns p_i + a_i; sums in
+// ascending order, one rounding per operation), sigma and Alg. 1.
 template <int N>
-__device__ __forceinline__ void lane_setup(LaneCell<N>& C, const double* rho_g,
-                                           const double* rho_d, const double* t_stop,
-                                           int64_t ld, int64_t c, double dt, int K,
-                                           int option) {
-  const double rg = rho_g[c];
-  C.bad = gas_bad(rg);
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const double t = t_stop[i * ld + c];
-    const double r = rho_d[i * ld + c];
-    C.bad |= species_bad(t, r);
-    const Species sp = species_coeffs(dt, t, r, rg);
-    C.a[i] = sp.a;
-    C.e[i] = sp.e;
-    C.p[i] = sp.p;
-  }
-  // ||A||_1: the gas column |A00| + a_1 + .. + a_N, the species columns
-  // p_i + a_i; sums in ascending order, one rounding per operation.
+__device__ __forceinline__ void lane_setup_norm(LaneCell<N>& C, int K, int option) {
   double s = 0.0, sig = 1.0;
   bool finite = true;
 #pragma unroll
@@ -137,6 +123,44 @@ __device__ __forceinline__ void lane_setup(LaneCell<N>& C, const double* rho_g,
     nrm = 0.0;
   }
   C.kms = select_kms(nrm, K, option);
+}
+
+// Set-up from memory; each species is loaded just before its coefficients.
+template <int N>
+__device__ __forceinline__ void lane_setup(LaneCell<N>& C, const double* rho_g,
+                                           const double* rho_d, const double* t_stop,
+                                           int64_t ld, int64_t c, double dt, int K,
+                                           int option) {
+  const double rg = rho_g[c];
+  C.bad = gas_bad(rg);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double t = t_stop[i * ld + c];
+    const double r = rho_d[i * ld + c];
+    C.bad |= species_bad(t, r);
+    const Species sp = species_coeffs(dt, t, r, rg);
+    C.a[i] = sp.a;
+    C.e[i] = sp.e;
+    C.p[i] = sp.p;
+  }
+  lane_setup_norm<N>(C, K, option);
+}
+
+// Set-up from inputs already in registers.
+template <int N>
+__device__ __forceinline__ void lane_setup_values(LaneCell<N>& C, double rg,
+                                                  const double (&rd)[N], const double (&ts)[N],
+                                                  double dt, int K, int option) {
+  C.bad = gas_bad(rg);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    C.bad |= species_bad(ts[i], rd[i]);
+    const Species sp = species_coeffs(dt, ts[i], rd[i], rg);
+    C.a[i] = sp.a;
+    C.e[i] = sp.e;
+    C.p[i] = sp.p;
+  }
+  lane_setup_norm<N>(C, K, option);
 }
 
 // Z = T_m(2^-s At)^(2^s) - I for the lane's cell.
@@ -165,6 +189,36 @@ __device__ __forceinline__ void lane_expm(double (&Z)[N][N], const LaneCell<N>& 
   if (it < s) {
     lane_square_to<N>(T, Z);
     lane_copy<N>(Z, T);
+  }
+}
+
+// v' = v + E v - v for component d of the lane's cell: u = Z dv on the
+// relative velocities, the gas by momentum conservation; NaN for a bad cell.
+template <int N>
+__device__ __forceinline__ void lane_apply_component(const CellArgs& A, const LaneCell<N>& C,
+                                                     const double (&Z)[N][N],
+                                                     const double (&v)[N + 1], int d, int64_t c,
+                                                     bool active) {
+  const int n1 = N + 1;
+  double dv[N], u[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) dv[j] = v[j + 1] - v[0];
+  double eu = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc = fma(Z[i][k], dv[k], acc);
+    u[i] = acc;
+    eu = fma(C.e[i], acc, eu);
+  }
+  const double d0 = -eu / C.sigma;
+  if (active) {
+    const double qnan = __builtin_nan("");
+    A.v_out[(int64_t)(d * n1) * A.ld + c] = C.bad ? qnan : v[0] + d0;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      A.v_out[(int64_t)(d * n1 + 1 + j) * A.ld + c] = C.bad ? qnan : v[j + 1] + (d0 + u[j]);
   }
 }
 
@@ -214,6 +268,98 @@ __device__ __forceinline__ void lane_forward_cell(const CellArgs& A, int64_t c, 
     }
   }
   if (C.bad && active) atomicOr(&g_status_word, C.bad);
+}
+
+// Coefficient inputs of one cell held in registers: gas and species
+// densities and stopping times; with the velocities (up to three
+// components) for the full prefetch.
+template <int N>
+struct LaneCoefs {
+  double rg, rd[N], ts[N];
+};
+template <int N>
+struct LaneInputs : LaneCoefs<N> {
+  double v[3][N + 1];
+};
+
+// Element `off / 8` of a row of `bytes` bytes through a raw buffer load: the
+// row's base lives in a scalar resource and every load of a cell shares one
+// 32-bit lane offset, so prefetching a cell's inputs holds one address
+// register, not a 64-bit address per row.  An offset past the row reads 0.
+__device__ __forceinline__ double row_at(const double* row, uint32_t bytes, uint32_t off) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(row), (short)0, (int)bytes, 0x00020000);
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// Inputs of cell c, given as the byte offset off = 8 c (c < n_cells <= 2^29).
+template <int N>
+__device__ __forceinline__ void lane_load(LaneCoefs<N>& X, const CellArgs& A, uint32_t off) {
+  const uint32_t bytes = (uint32_t)(8 * A.n_cells);
+  X.rg = row_at(A.rho_g, bytes, off);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    X.ts[i] = row_at(A.t_stop + i * A.ld, bytes, off);
+    X.rd[i] = row_at(A.rho_d + i * A.ld, bytes, off);
+  }
+}
+
+// ... and the velocities; components past n_dim repeat the last one (cache
+// hits, never used), which keeps the loads unconditional.
+template <int N>
+__device__ __forceinline__ void lane_load(LaneInputs<N>& X, const CellArgs& A, uint32_t off) {
+  lane_load<N>(static_cast<LaneCoefs<N>&>(X), A, off);
+  const uint32_t bytes = (uint32_t)(8 * A.n_cells);
+  const int n1 = N + 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int dd = d < A.n_dim ? d : A.n_dim - 1;
+#pragma unroll
+    for (int j = 0; j <= N; ++j) X.v[d][j] = row_at(A.v_in + (int64_t)(dd * n1 + j) * A.ld, bytes, off);
+  }
+}
+
+// Streaming form of the one-lane forward.  The one-shot grid runs its
+// wavefronts in lock-step generations (all load, then all compute while HBM
+// idles, then all store), so its time is the sum of the memory and the
+// arithmetic phases.  Here a grid of at most the resident wavefronts walks
+// the cells with a stride, and each lane loads the inputs of its next cell
+// before it computes the current one: the loads of one cell overlap the
+// arithmetic of the previous.  Same arithmetic as k_forward_lane, per cell.
+// Needs n_cells <= 2^29 (32-bit byte offsets of the lanes).
+template <int N>
+__global__ void __launch_bounds__(256) k_forward_lane_stream(CellArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = A.n_cells;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t w0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);  // the wavefront's first cell
+  if (w0 >= n) return;                                             // uniform over the wavefront
+  LaneInputs<N> cur;
+  lane_load<N>(cur, A, (uint32_t)(8 * (w0 + lane < n ? w0 + lane : w0)));
+  for (;;) {
+    const int64_t c = w0 + lane;
+    const bool active = c < n;
+    const int64_t w1 = w0 + stride;  // uniform: the loop and the prefetch branch
+    LaneInputs<N> nxt;
+    if (w1 < n) lane_load<N>(nxt, A, (uint32_t)(8 * (w1 + lane < n ? w1 + lane : w1)));
+    LaneCell<N> C;
+    lane_setup_values<N>(C, cur.rg, cur.rd, cur.ts, A.dt, A.k_max, A.option);
+    double Z[N][N];
+    lane_expm<N>(Z, C);
+    bool vfin = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int j = 0; j <= N; ++j) vfin = vfin && isfinite(cur.v[d][j]);
+    if (!vfin && !C.bad) C.bad = kBadVelocity;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (d < A.n_dim) lane_apply_component<N>(A, C, Z, cur.v[d], d, c, active);
+    if (C.bad && active) atomicOr(&g_status_word, C.bad);
+    if (w1 >= n) break;
+    cur = nxt;
+    w0 = w1;
+  }
 }
 
 template <int N>

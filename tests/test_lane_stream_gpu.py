@@ -1,0 +1,91 @@
+"""GPU parity of the streaming one-lane forward (N = 5..8), at sizes past one
+pass of the resident grid: every wavefront walks several cells and loads
+the next cell's inputs while it computes the current one.  Ragged tails,
+one to three velocity components, a padded leading dimension, in place, and
+bad cells placed in different passes.  Same bar as the other parity tests
+(the method oracle, max(1e-13, 4 u ||dt K||_1) per cell; momentum 1e-12).
+"""
+import numpy as np
+import pytest
+
+from paper_2509_25347_amd import workloads as W
+from test_parity_gpu import assert_parity, cell_errors, run
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_25347_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ops(dev):
+    from paper_2509_25347_amd import ops as _ops
+    return _ops
+
+
+def _make(N, cells, D):
+    return W.make_stiff(N, cells, D=D) if N % 2 == 0 else W.make_jittered(N, cells, D=D)
+
+
+@pytest.mark.parametrize("N,D,cells", [(5, 3, 300_007), (6, 2, 270_001), (7, 1, 200_003),
+                                       (8, 3, 200_003)])
+def test_multi_pass_parity(ops, dev, orc, N, D, cells):
+    d = _make(N, cells, D)
+    ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"])
+    print(f"stream parity N={N} D={D} cells={cells}", flush=True)
+    got = run(ops, d, dev)
+    assert_parity(got, ref, nrm, d, f"N={N} D={D}", truth=False)
+
+
+@pytest.mark.parametrize("N", [5, 8])
+def test_in_place_and_padded_ld_bit_equal(ops, dev, N):
+    cells, ld = 150_001, 150_080
+    d = _make(N, cells, 3)
+    T = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev)
+         for k in ("rho_g", "rho_d", "t_stop", "v")}
+    print(f"stream in place / padded ld N={N}", flush=True)
+    base = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"])
+    inplace = T["v"].clone()
+    ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], inplace, d["dt"], out=inplace)
+
+    def padded(x):
+        p = torch.full(x.shape[:-1] + (ld,), float("nan"), dtype=x.dtype, device=dev)
+        p[..., :cells] = x
+        return p[..., :cells]
+
+    rd, ts, v = padded(T["rho_d"]), padded(T["t_stop"]), padded(T["v"])
+    out = padded(torch.zeros_like(T["v"]))
+    ops.expm_apply(T["rho_g"], rd, ts, v, d["dt"], out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(base, inplace)
+    assert torch.equal(base, out)
+
+
+def test_bad_cells_in_different_passes(ops, dev, orc):
+    N, cells = 8, 200_003
+    d = _make(N, cells, 3)
+    rg, rd, ts, v = (d[k].copy() for k in ("rho_g", "rho_d", "t_stop", "v"))
+    bad = {5: "rho_g", 70_000: "t", 140_001: "v", cells - 1: "rho_d"}
+    rg[5] = 0.0
+    ts[3, 70_000] = np.nan
+    v[2, 4, 140_001] = np.inf
+    rd[7, cells - 1] = -1.0
+    ref, kms, nrm, st = orc.apply_cells(rg, rd, ts, v, d["dt"])
+    print("stream bad cells N=8", flush=True)
+    ops.clear_status()
+    got = run(ops, dict(rho_g=rg, rho_d=rd, t_stop=ts, v=v, dt=d["dt"]), dev)
+    status = ops.get_status()
+    assert status == st == (orc.BAD_DENSITY | orc.BAD_STOPPING_TIME | orc.BAD_VELOCITY)
+    for c in bad:
+        assert np.isnan(got[:, :, c]).all(), c
+    good = np.setdiff1d(np.arange(cells), list(bad))
+    e = cell_errors(got[..., good], ref[..., good], v[..., good])
+    assert (e <= np.maximum(4 * U * nrm[good], 1e-13)).all()
