@@ -137,8 +137,11 @@ static int resident_blocks(const void* kernel, std::atomic<int>& per_cu, int* ou
 // a grid of the resident wavefronts) for N = 5..8, where each wavefront
 // holds many registers and few fit on a SIMD, and the one-shot kernel for
 // N <= 4, where enough wavefronts are resident to hide the loads and the
-// extra registers of the prefetch would halve them (measured, 2^20 cells).
+// extra registers of the prefetch would halve them; there, all loads up
+// front except at N = 3, where the velocities' registers would cut the
+// resident wavefronts from 8 to 5 (measured, 2^20 cells).
 constexpr int kLaneStreamMinN = 5;
+constexpr bool lane_early_loads(int n) { return n == 1 || n == 2 || n == 4; }
 
 template <int N>
 static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
@@ -156,6 +159,13 @@ static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
     }
   }
   const Grid gr = grid_for((A.n_cells + 255) / 256);
+  if constexpr (lane_early_loads(N)) {
+    if (A.n_cells <= (int64_t(1) << 29)) {
+      hipLaunchKernelGGL((k_forward_lane<N, true>), dim3(gr.blocks), dim3(256), 0, st, A,
+                         gr.xcd_blocks);
+      return hip_status(hipGetLastError());
+    }
+  }
   hipLaunchKernelGGL(k_forward_lane<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
   return hip_status(hipGetLastError());
 }

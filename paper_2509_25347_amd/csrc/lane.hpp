@@ -319,6 +319,27 @@ __device__ __forceinline__ void lane_load(LaneInputs<N>& X, const CellArgs& A, u
   }
 }
 
+// The forward update of cell c from inputs already in registers (all lanes
+// of the wavefront together, as lane_forward_cell).
+template <int N>
+__device__ __forceinline__ void lane_forward_loaded(const CellArgs& A, const LaneInputs<N>& X,
+                                                   int64_t c, bool active) {
+  LaneCell<N> C;
+  lane_setup_values<N>(C, X.rg, X.rd, X.ts, A.dt, A.k_max, A.option);
+  double Z[N][N];
+  lane_expm<N>(Z, C);
+  bool vfin = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int j = 0; j <= N; ++j) vfin = vfin && isfinite(X.v[d][j]);
+  if (!vfin && !C.bad) C.bad = kBadVelocity;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (d < A.n_dim) lane_apply_component<N>(A, C, Z, X.v[d], d, c, active);
+  if (C.bad && active) atomicOr(&g_status_word, C.bad);
+}
+
 // Streaming form of the one-lane forward.  The one-shot grid runs its
 // wavefronts in lock-step generations (all load, then all compute while HBM
 // idles, then all store), so its time is the sum of the memory and the
@@ -342,27 +363,18 @@ __global__ void __launch_bounds__(256) k_forward_lane_stream(CellArgs A) {
     const int64_t w1 = w0 + stride;  // uniform: the loop and the prefetch branch
     LaneInputs<N> nxt;
     if (w1 < n) lane_load<N>(nxt, A, (uint32_t)(8 * (w1 + lane < n ? w1 + lane : w1)));
-    LaneCell<N> C;
-    lane_setup_values<N>(C, cur.rg, cur.rd, cur.ts, A.dt, A.k_max, A.option);
-    double Z[N][N];
-    lane_expm<N>(Z, C);
-    bool vfin = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int j = 0; j <= N; ++j) vfin = vfin && isfinite(cur.v[d][j]);
-    if (!vfin && !C.bad) C.bad = kBadVelocity;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      if (d < A.n_dim) lane_apply_component<N>(A, C, Z, cur.v[d], d, c, active);
-    if (C.bad && active) atomicOr(&g_status_word, C.bad);
+    lane_forward_loaded<N>(A, cur, c, active);
     if (w1 >= n) break;
     cur = nxt;
     w0 = w1;
   }
 }
 
-template <int N>
+// One-shot one-lane forward.  EARLY issues every load of the cell, the
+// velocities included, before the exponential, so that they arrive during
+// it (n_cells <= 2^29); otherwise the velocities are read after it, which
+// keeps fewer registers live.
+template <int N, bool EARLY = false>
 __global__ void __launch_bounds__(256) k_forward_lane(CellArgs A, int xcd_blocks) {
   // XCD-aware order: consecutive workgroup ids go to different XCDs, so
   // hand each XCD a contiguous range of cells.
@@ -370,7 +382,13 @@ __global__ void __launch_bounds__(256) k_forward_lane(CellArgs A, int xcd_blocks
   const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
   const int64_t c = logical * 256 + threadIdx.x;
   const bool active = c < A.n_cells;
-  lane_forward_cell<N>(A, c, active ? c : 0, active);
+  if constexpr (EARLY) {
+    LaneInputs<N> X;
+    lane_load<N>(X, A, (uint32_t)(8 * (active ? c : 0)));
+    lane_forward_loaded<N>(A, X, c, active);
+  } else {
+    lane_forward_cell<N>(A, c, active ? c : 0, active);
+  }
 }
 
 }  // namespace dragexp

@@ -1,8 +1,10 @@
-"""GPU parity of the streaming one-lane forward (N = 5..8), at sizes past one
-pass of the resident grid: every wavefront walks several cells and loads
-the next cell's inputs while it computes the current one.  Ragged tails,
-one to three velocity components, a padded leading dimension, in place, and
-bad cells placed in different passes.  Same bar as the other parity tests
+"""GPU parity of the one-lane forward's load schedules: the streaming kernel
+(N = 5..8) at sizes past one pass of the resident grid, where every
+wavefront walks several cells and loads the next cell's inputs while it
+computes the current one, and the one-shot kernel that issues all of a
+cell's loads before the exponential (N = 1, 2, 4).  Ragged tails, one to
+three velocity components, a padded leading dimension, in place, and bad
+cells placed in different passes.  Same bar as the other parity tests
 (the method oracle, max(1e-13, 4 u ||dt K||_1) per cell; momentum 1e-12).
 """
 import numpy as np
@@ -36,7 +38,8 @@ def _make(N, cells, D):
 
 
 @pytest.mark.parametrize("N,D,cells", [(5, 3, 300_007), (6, 2, 270_001), (7, 1, 200_003),
-                                       (8, 3, 200_003)])
+                                       (8, 3, 200_003), (1, 1, 50_001), (2, 3, 70_001),
+                                       (4, 2, 100_003), (4, 3, 65_536)])
 def test_multi_pass_parity(ops, dev, orc, N, D, cells):
     d = _make(N, cells, D)
     ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"])
@@ -45,7 +48,7 @@ def test_multi_pass_parity(ops, dev, orc, N, D, cells):
     assert_parity(got, ref, nrm, d, f"N={N} D={D}", truth=False)
 
 
-@pytest.mark.parametrize("N", [5, 8])
+@pytest.mark.parametrize("N", [1, 4, 5, 8])
 def test_in_place_and_padded_ld_bit_equal(ops, dev, N):
     cells, ld = 150_001, 150_080
     d = _make(N, cells, 3)
