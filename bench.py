@@ -87,7 +87,7 @@ def forward_kernel(N, mapping, n_cells):
     if N <= 4:
         return "k_forward_lane"
     if N <= 8:
-        return "k_forward_lane_stream" if n_cells <= 1 << 29 else "k_forward_lane"
+        return "k_forward_lane_stream" if n_cells < 1 << 29 else "k_forward_lane"
     return "k_forward_pair"
 
 

@@ -146,7 +146,7 @@ constexpr bool lane_early_loads(int n) { return n == 1 || n == 2 || n == 4; }
 template <int N>
 static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
   if constexpr (N >= kLaneStreamMinN) {
-    if (A.n_cells <= (int64_t(1) << 29)) {  // 32-bit lane byte offsets
+    if (A.n_cells < (int64_t(1) << 29)) {  // 32-bit lane byte offsets
       static std::atomic<int> per_cu{0};
       int resident = 0;
       const int rc = resident_blocks(reinterpret_cast<const void*>(&k_forward_lane_stream<N>),
@@ -160,7 +160,7 @@ static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
   }
   const Grid gr = grid_for((A.n_cells + 255) / 256);
   if constexpr (lane_early_loads(N)) {
-    if (A.n_cells <= (int64_t(1) << 29)) {
+    if (A.n_cells < (int64_t(1) << 29)) {
       hipLaunchKernelGGL((k_forward_lane<N, true>), dim3(gr.blocks), dim3(256), 0, st, A,
                          gr.xcd_blocks);
       return hip_status(hipGetLastError());

@@ -292,7 +292,8 @@ __device__ __forceinline__ double row_at(const double* row, uint32_t bytes, uint
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
-// Inputs of cell c, given as the byte offset off = 8 c (c < n_cells <= 2^29).
+// Inputs of cell c, given as the byte offset off = 8 c (c < n_cells < 2^29,
+// so that 8 n_cells fits in 32 bits).
 template <int N>
 __device__ __forceinline__ void lane_load(LaneCoefs<N>& X, const CellArgs& A, uint32_t off) {
   const uint32_t bytes = (uint32_t)(8 * A.n_cells);
@@ -347,7 +348,7 @@ __device__ __forceinline__ void lane_forward_loaded(const CellArgs& A, const Lan
 // the cells with a stride, and each lane loads the inputs of its next cell
 // before it computes the current one: the loads of one cell overlap the
 // arithmetic of the previous.  Same arithmetic as k_forward_lane, per cell.
-// Needs n_cells <= 2^29 (32-bit byte offsets of the lanes).
+// Needs n_cells < 2^29 (32-bit byte offsets and row sizes).
 template <int N>
 __global__ void __launch_bounds__(256) k_forward_lane_stream(CellArgs A) {
   const int lane = threadIdx.x & 63;
@@ -372,7 +373,7 @@ __global__ void __launch_bounds__(256) k_forward_lane_stream(CellArgs A) {
 
 // One-shot one-lane forward.  EARLY issues every load of the cell, the
 // velocities included, before the exponential, so that they arrive during
-// it (n_cells <= 2^29); otherwise the velocities are read after it, which
+// it (n_cells < 2^29); otherwise the velocities are read after it, which
 // keeps fewer registers live.
 template <int N, bool EARLY = false>
 __global__ void __launch_bounds__(256) k_forward_lane(CellArgs A, int xcd_blocks) {
