@@ -76,6 +76,7 @@ KERNEL_SOURCES = {"k_forward_wave": ("common.hpp", "wave.hpp"),
                   "k_forward_lane": ("common.hpp", "lane.hpp"),
                   "k_forward_lane_stream": ("common.hpp", "lane.hpp"),
                   "k_forward_pair": ("common.hpp", "lane.hpp", "pair.hpp"),
+                  "k_backward_pair": ("common.hpp", "lane.hpp", "pair.hpp"),
                   "k_forward_big": ("common.hpp", "wave.hpp", "big.hpp"),
                   "k_rk1_lane": ("common.hpp", "rk1.hpp")}
 

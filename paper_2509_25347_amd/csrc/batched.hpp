@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(256) k_batched_lane(BatchArgs B) {
 
 // One 32-cell item per wavefront, two lanes per cell (N = 9..12).
 template <int N>
-__global__ void __launch_bounds__(256) k_batched_pair(BatchArgs B) {
+__global__ void __launch_bounds__(256, pair_fwd_min_waves<N>()) k_batched_pair(BatchArgs B) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int idx = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
   if (idx >= B.n_items) return;  // uniform over the wavefront

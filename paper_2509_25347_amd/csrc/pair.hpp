@@ -221,6 +221,14 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
       for (int r = 0; r < H; ++r)
 #pragma unroll
         for (int k = 0; k < W2; ++k) dY[r][k] = T[r][k];
+      // An empty asm that "rewrites" Y: the partner's copies of Y fetched for
+      // dY above are fetched again below instead of being kept live across
+      // the copy (2 H W2 more registers, which spilled: 33 VGPRs at N = 8,
+      // 28-30 at N = 9, 10; the refetch is 8-14 % faster, same bits).
+#pragma unroll
+      for (int r = 0; r < H; ++r)
+#pragma unroll
+        for (int k = 0; k < W2; ++k) asm volatile("" : "+v"(Y[r][k]));
       // Y <- Y (Y + 2I)
 #pragma unroll
       for (int r = 0; r < H; ++r)
@@ -493,8 +501,16 @@ __device__ __forceinline__ void pair_forward_cell(const CellArgs& A, int64_t c, 
   if (C.bad && active && h == 0) atomicOr(&g_status_word, C.bad);
 }
 
+// Waves per SIMD the forward's register allocation must allow: 2 up to
+// N = 10 (a few VGPRs spill, and the second wavefront hides the latencies:
+// 1.27-1.36x faster than 1 wave with accumulation registers), 1 above
+// (Z and the product buffer alone fill 256 registers).
 template <int N>
-__global__ void __launch_bounds__(256) k_forward_pair(CellArgs A, int xcd_blocks) {
+constexpr int pair_fwd_min_waves() { return N <= 10 ? 2 : 1; }
+
+template <int N>
+__global__ void __launch_bounds__(256, pair_fwd_min_waves<N>()) k_forward_pair(CellArgs A,
+                                                                              int xcd_blocks) {
   constexpr int kCells = 128;  // cells per workgroup, two lanes each
   const int bid = blockIdx.x;
   const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
