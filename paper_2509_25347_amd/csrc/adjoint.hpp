@@ -28,8 +28,11 @@ namespace dragexp {
 
 // ---- one cell per lane --------------------------------------------------------
 
+// At N = 6 the kernel needs 291 registers (1 wave/SIMD); bounding it to 2
+// waves spills 63 VGPRs to scratch and still runs 13-17 % faster.  At N = 7
+// the same bound spills 438 and runs 2.9x slower, so it keeps 1.
 template <int N>
-__global__ void __launch_bounds__(256) k_backward_lane(BackArgs A, int xcd_blocks) {
+__global__ void __launch_bounds__(256, N == 6 ? 2 : 1) k_backward_lane(BackArgs A, int xcd_blocks) {
   const int bid = blockIdx.x;
   const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
   const int64_t c = logical * 256 + threadIdx.x;
