@@ -85,7 +85,7 @@ def forward_kernel(N, mapping, n_cells):
     """The kernel drag_expm_apply launches for N species under `mapping`."""
     if mapping == "wave":
         return "k_forward_wave" if N <= 16 else "k_forward_big"
-    if N <= 4:
+    if N <= 6:
         return "k_forward_lane"
     if N <= 8:
         return "k_forward_lane_stream" if n_cells < 1 << 29 else "k_forward_lane"

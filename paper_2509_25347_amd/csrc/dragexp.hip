@@ -134,14 +134,14 @@ static int resident_blocks(const void* kernel, std::atomic<int>& per_cu, int* ou
 }
 
 // The one-lane forward: the streaming kernel (prefetch of the next cell,
-// a grid of the resident wavefronts) for N = 5..8, where each wavefront
-// holds many registers and few fit on a SIMD, and the one-shot kernel for
-// N <= 4, where enough wavefronts are resident to hide the loads and the
-// extra registers of the prefetch would halve them; there, all loads up
+// a grid of the resident wavefronts) for N = 7, 8, where few wavefronts fit
+// on a SIMD (2 and 1) to hide the loads; the one-shot kernel below, where
+// enough are resident and the prefetch registers would cut them (1.03-1.17x
+// slower at N = 5, 6).  The one-shot kernel issues all of a cell's loads up
 // front except at N = 3, where the velocities' registers would cut the
-// resident wavefronts from 8 to 5 (measured, 2^20 cells).
-constexpr int kLaneStreamMinN = 5;
-constexpr bool lane_early_loads(int n) { return n == 1 || n == 2 || n == 4; }
+// resident wavefronts from 8 to 5 (interleaved timings, 2^18-2^20 cells).
+constexpr int kLaneStreamMinN = 7;
+constexpr bool lane_early_loads(int n) { return n != 3 && n < kLaneStreamMinN; }
 
 template <int N>
 static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
