@@ -38,8 +38,11 @@ def _ld_of(t, rows_dims, name):
     """Leading dimension of an SoA array whose last axis is the cell axis."""
     if t.stride(-1) != 1:
         raise ValueError(f"{name}: the cell axis must be contiguous")
-    if t.dim() == 1:
-        return None
+    rows = 1
+    for n in t.shape[:-1]:
+        rows *= n
+    if rows <= 1:
+        return None  # one row (rho_g; rho_d at N = 1): its row stride is never used
     ld = t.stride(-2)
     # all rows equally spaced by ld
     exp = 1

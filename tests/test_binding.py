@@ -28,3 +28,14 @@ def test_layout_helpers_reject_uneven_rows():
     y = torch.zeros((3, 6, 40), dtype=torch.float64)[:, :5, :]  # rows spaced 40, blocks 240
     with pytest.raises(ValueError):
         ops._ld_of(y, 2, "y")
+
+
+def test_a_single_row_imposes_no_leading_dimension():
+    """rho_d and t_stop at N = 1 are one row: a view of a wider array (row
+    stride != C) must not clash with v's leading dimension."""
+    from paper_2509_25347_amd import ops
+    wide = torch.zeros((1, 1000), dtype=torch.float64)[:, :300]
+    assert wide.stride(0) == 1000
+    assert ops._ld_of(wide, 1, "rho_d") is None
+    v = torch.zeros((3, 2, 300), dtype=torch.float64)
+    assert ops._ld_of(v, 2, "v") == 300

@@ -127,3 +127,23 @@ print("ok", flush=True)
     print("stream first call under capture (subprocess)", flush=True)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=150)
     assert r.returncode == 0 and "ok" in r.stdout, (r.returncode, r.stdout[-1000:], r.stderr[-3000:])
+
+
+@pytest.mark.parametrize("N", [1, 3, 4, 6, 7, 8, 9, 11, 13, 16])
+def test_results_do_not_depend_on_the_launch(ops, dev, N):
+    """Cells are independent: the first 3001 cells of a 200_003-cell launch
+    (several passes of the streaming grid, or a large one-shot grid) carry
+    the same bits as a launch of those 3001 cells alone, and a second launch
+    repeats the first bit for bit."""
+    d = _make(N, 200_003, 3)
+    T = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev)
+         for k in ("rho_g", "rho_d", "t_stop", "v")}
+    print(f"launch independence N={N}", flush=True)
+    full = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"])
+    again = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"])
+    k = 3001
+    sub = {n: T[n][..., :k].contiguous() for n in T}
+    part = ops.expm_apply(sub["rho_g"], sub["rho_d"], sub["t_stop"], sub["v"], d["dt"])
+    torch.cuda.synchronize()
+    assert torch.equal(full, again)
+    assert torch.equal(full[..., :k], part)
