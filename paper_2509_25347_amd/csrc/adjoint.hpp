@@ -516,8 +516,10 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
   }
 }
 
+// 3 waves/SIMD: 23 VGPRs spill (194 registers otherwise, 2 waves), and the
+// third wavefront still makes it 5-7 % faster (interleaved timings, N = 11-16).
 template <int N>
-__global__ void __launch_bounds__(256) k_backward_wave(BackArgs A, int xcd_blocks) {
+__global__ void __launch_bounds__(256, 3) k_backward_wave(BackArgs A, int xcd_blocks) {
   // per wavefront: the quad block (staging tile + coefficient tables) and a
   // second staging tile
   __shared__ double lds[4 * (kQuadDoubles + kStageDoubles)];
