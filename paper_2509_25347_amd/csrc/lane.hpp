@@ -286,9 +286,12 @@ struct LaneInputs : LaneCoefs<N> {
 // row's base lives in a scalar resource and every load of a cell shares one
 // 32-bit lane offset, so prefetching a cell's inputs holds one address
 // register, not a 64-bit address per row.  An offset past the row reads 0.
+// The resource: stride 0 (raw), num_records = bytes (bit pattern; up to
+// 2^32 - 8 here), and the CDNA word-3 flags for 32-bit untyped data.
 __device__ __forceinline__ double row_at(const double* row, uint32_t bytes, uint32_t off) {
-  const __amdgpu_buffer_rsrc_t r =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(row), (short)0, (int)bytes, 0x00020000);
+  constexpr int kRawBufferFlags = 0x00020000;
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(row), (short)0, (int)bytes, kRawBufferFlags);
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
