@@ -147,3 +147,30 @@ def test_results_do_not_depend_on_the_launch(ops, dev, N):
     torch.cuda.synchronize()
     assert torch.equal(full, again)
     assert torch.equal(full[..., :k], part)
+
+
+@pytest.mark.parametrize("N", [3, 6, 8, 10, 12])
+def test_adjoint_does_not_depend_on_the_launch(ops, dev, N):
+    """The fused forward + adjoint of the first 2001 cells of a 100_003-cell
+    launch equals that of a launch of those cells alone, bit for bit, and a
+    second launch repeats the first."""
+    d = _make(N, 100_003, 3)
+    w = np.random.default_rng(N).standard_normal(d["v"].shape)
+    T = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev)
+         for k in ("rho_g", "rho_d", "t_stop", "v")}
+    T["w"] = torch.from_numpy(w).to(dev)
+    print(f"adjoint launch independence N={N}", flush=True)
+
+    def run_bwd(X):
+        return ops.expm_apply_backward(X["rho_g"], X["rho_d"], X["t_stop"], X["v"], X["w"],
+                                       d["dt"])
+
+    full, again = run_bwd(T), run_bwd(T)
+    k = 2001
+    part = run_bwd({n: T[n][..., :k].contiguous() for n in T})
+    torch.cuda.synchronize()
+    for a, b, p in zip(full, again, part):
+        if a is None:
+            continue
+        assert torch.equal(a, b)
+        assert torch.equal(a[..., :k], p)
