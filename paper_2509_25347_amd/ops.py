@@ -16,9 +16,19 @@ import torch
 from . import _lib
 
 
+# torch's raw accessor of the current stream: torch.cuda.current_stream()
+# builds a Python stream object per call (about 3 us, as long as a small
+# launch), the accessor returns the handle itself.
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream_ptr(stream=None):
-    s = torch.cuda.current_stream() if stream is None else stream
-    return ctypes.c_void_p(s.cuda_stream)
+    """`stream`, else torch's current stream on the current device."""
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
+    if _raw_stream is not None:
+        return ctypes.c_void_p(_raw_stream(torch.cuda.current_device()))
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def _ptr(t):
@@ -28,47 +38,45 @@ def _ptr(t):
 def _require(t, name):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
-    if t.dtype != torch.float64:
+    if t.dtype is not torch.float64:
         raise TypeError(f"{name} must be float64 (got {t.dtype}); there is no implicit cast")
-    if t.device.type != "cuda":
+    if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor")
 
 
 def _ld_of(t, rows_dims, name):
     """Leading dimension of an SoA array whose last axis is the cell axis."""
-    if t.stride(-1) != 1:
+    st, sh = t.stride(), t.shape
+    if st[-1] != 1:
         raise ValueError(f"{name}: the cell axis must be contiguous")
     rows = 1
-    for n in t.shape[:-1]:
+    for n in sh[:-1]:
         rows *= n
     if rows <= 1:
         return None  # one row (rho_g; rho_d at N = 1): its row stride is never used
-    ld = t.stride(-2)
+    ld = st[-2]
     # all rows equally spaced by ld
     exp = 1
-    for ax in range(t.dim() - 2, -1, -1):
-        if t.size(ax) > 1 and t.stride(ax) != ld * exp:
+    for ax in range(len(sh) - 2, -1, -1):
+        if sh[ax] > 1 and st[ax] != ld * exp:
             raise ValueError(f"{name}: rows must be equally spaced (stride ld)")
-        exp *= t.size(ax)
+        exp *= sh[ax]
     return ld
 
 
 def _shapes(rho_g, rho_d, t_stop, v):
     for x, n in ((rho_g, "rho_g"), (rho_d, "rho_d"), (t_stop, "t_stop"), (v, "v")):
         _require(x, n)
-    if rho_g.dim() != 1 or rho_d.dim() != 2 or t_stop.dim() != 2 or v.dim() != 3:
+    sg, sd, st, sv = rho_g.shape, rho_d.shape, t_stop.shape, v.shape
+    if len(sg) != 1 or len(sd) != 2 or len(st) != 2 or len(sv) != 3:
         raise ValueError("expected rho_g [C], rho_d [N][C], t_stop [N][C], v [D][N+1][C]")
-    C = rho_g.size(0)
-    N = rho_d.size(0)
-    D = v.size(0)
-    if rho_d.shape != (N, C) or t_stop.shape != (N, C) or v.shape != (D, N + 1, C):
+    C, N, D = sg[0], sd[0], sv[0]
+    if sd != (N, C) or st != (N, C) or sv != (D, N + 1, C):
         raise ValueError("inconsistent shapes")
     if rho_g.stride(0) != 1:
         raise ValueError("rho_g must be contiguous")
     lds = {x for x in (_ld_of(rho_d, 1, "rho_d"), _ld_of(t_stop, 1, "t_stop"),
                        _ld_of(v, 2, "v")) if x is not None}
-    if N == 1 and D == 1:
-        lds.add(C)
     if len(lds) > 1:
         raise ValueError("rho_d, t_stop and v must share one leading dimension")
     ld = lds.pop() if lds else C
