@@ -174,3 +174,15 @@ def test_adjoint_does_not_depend_on_the_launch(ops, dev, N):
             continue
         assert torch.equal(a, b)
         assert torch.equal(a[..., :k], p)
+
+
+@pytest.mark.parametrize("N", [7, 8])
+@pytest.mark.parametrize("cells", [1, 63, 64, 65, 257, 65_536, 65_537, 131_073])
+def test_stream_sizes_at_the_pass_boundaries(ops, dev, orc, N, cells):
+    """Sizes around a wavefront, a workgroup and one or two passes of the
+    resident grid (65 536 cells at one wavefront per SIMD on 256 CUs)."""
+    d = _make(N, cells, 3)
+    ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"])
+    print(f"stream sizes N={N} cells={cells}", flush=True)
+    got = run(ops, d, dev)
+    assert_parity(got, ref, nrm, d, f"N={N} cells={cells}", truth=False)
