@@ -156,6 +156,12 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="time the fused forward + adjoint (drag_expm_apply_backward) on the "
                          "workload instead of the forward (for profiling the adjoint kernels)")
+    ap.add_argument("--batched", action="store_true",
+                    help="time only the batched uneven-N graph (4096 blocks x 512 cells, K = 9, "
+                         "autotuned) for profiling its kernels")
+    ap.add_argument("--pin", default=None,
+                    help="with --batched: LANE_MAX,MODE (e.g. 10,per_n) instead of the "
+                         "autotuner's choice, so that profiling runs launch the same kernels")
     ap.add_argument("--rk1", action="store_true",
                     help="time the backward Euler step (drag_rk1_apply) on the workload instead "
                          "of the exponential, with its HBM roofline")
@@ -201,6 +207,9 @@ def main():
         return
     if args.adjoint:
         print(json.dumps(adjoint_only(torch, ops, _lib, workloads, dev, name, args)), flush=True)
+        return
+    if args.batched:
+        print(json.dumps(batched_only(torch, ops, workloads, dev, args)), flush=True)
         return
     if args.rk1:
         print(json.dumps(rk1_only(torch, ops, workloads, dev, name, args)), flush=True)
@@ -474,6 +483,29 @@ def adjoint_only(torch, ops, _lib, workloads, dev, name, args):
             "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": name, "n_cells": C, "n_species": N}}
+
+
+def batched_only(torch, ops, workloads, dev, args):
+    """The batched uneven-N graph alone (K = 9, the plan autotuned on the
+    data first, outside the timed launches)."""
+    batch = workloads.make_batched()
+    plan = ops.BatchPlan(batch["n_species"], batch["block_cells"], 3, batch["dt"], k_max=9)
+    fields, v = plan.pack(batch["blocks"], dev)
+    out = torch.empty_like(v)
+    if args.pin:
+        lm, mode = args.pin.split(",")
+        plan.set_config(int(lm), mode)
+    else:
+        plan.autotune(fields, v, out)
+    lane_max, mfma_mode = plan.config()
+    ms = _time(torch, lambda: plan.apply(fields, v, out), args.steps, args.warmup)
+    plan.close()
+    cells = len(batch["blocks"]) * batch["block_cells"]
+    return {"metric": "FP64 cell-updates/s of the batched uneven-N graph", "value": cells / (ms * 1e-3),
+            "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "4096 blocks x 512 cells, N_b ~ U{1..16}, D = 3",
+                       "n_cells": cells, "lane_max": lane_max, "mfma_mode": mfma_mode}}
 
 
 def n_sweep(torch, ops, _lib, workloads, dev, cells=1 << 18):
