@@ -54,6 +54,8 @@ def test_forward_kernel_names():
     assert bench.forward_kernel(16, "wave", 1 << 20) == "k_forward_wave"
     assert bench.forward_kernel(20, "wave", 1 << 18) == "k_forward_big"
     assert bench.forward_kernel(4, "lane", 1 << 20) == "k_forward_lane"
+    assert bench.forward_kernel(6, "lane", 1 << 20) == "k_forward_lane"
+    assert bench.forward_kernel(7, "lane", 1 << 20) == "k_forward_lane_stream"
     assert bench.forward_kernel(8, "lane", 1 << 18) == "k_forward_lane_stream"
     assert bench.forward_kernel(8, "lane", 1 << 29) == "k_forward_lane"
     assert bench.forward_kernel(10, "lane", 1 << 18) == "k_forward_pair"
