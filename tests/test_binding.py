@@ -39,3 +39,23 @@ def test_a_single_row_imposes_no_leading_dimension():
     assert ops._ld_of(wide, 1, "rho_d") is None
     v = torch.zeros((3, 2, 300), dtype=torch.float64)
     assert ops._ld_of(v, 2, "v") == 300
+
+
+def test_shapes_share_one_leading_dimension(monkeypatch):
+    """_shapes on host tensors (the device check switched off): a padded v
+    sets ld even at N = 1, D = 1; mismatched row strides are refused."""
+    from paper_2509_25347_amd import ops
+    monkeypatch.setattr(ops, "_require", lambda t, name: None)
+    C, ld = 100, 128
+    rho_g = torch.zeros(C, dtype=torch.float64)
+    rho_d = torch.zeros((1, 1000), dtype=torch.float64)[:, :C]  # one row: no constraint
+    t_stop = torch.zeros((1, C), dtype=torch.float64)
+    v = torch.zeros((1, 2, ld), dtype=torch.float64)[..., :C]
+    assert ops._shapes(rho_g, rho_d, t_stop, v) == (C, 1, 1, ld)
+    rho_d4 = torch.zeros((4, ld), dtype=torch.float64)[:, :C]
+    t4 = torch.zeros((4, C), dtype=torch.float64)  # ld C against ld 128
+    v4 = torch.zeros((3, 5, ld), dtype=torch.float64)[..., :C]
+    with pytest.raises(ValueError):
+        ops._shapes(rho_g, rho_d4, t4, v4)
+    t4p = torch.zeros((4, ld), dtype=torch.float64)[:, :C]
+    assert ops._shapes(rho_g, rho_d4, t4p, v4) == (C, 4, 3, ld)
