@@ -87,6 +87,10 @@ def _load():
     lib.truth_expm_eigen.restype = i
     lib.truth_expm_taylor.argtypes = [i, vp, i, vp]
     lib.truth_expm_taylor.restype = i
+    lib.truth_expm_general.argtypes = [i, d, d, vp, vp, vp]
+    lib.truth_expm_general.restype = i
+    lib.truth_apply_cells.argtypes = [i64, i, i, i64, d, vp, vp, vp, vp, vp]
+    lib.truth_apply_cells.restype = i
     _lib = lib
     return lib
 
@@ -236,6 +240,36 @@ def truth_eigen(dt, rho_g, rho_d, t_stop):
     if rc != 0:
         raise ValueError("truth_expm_eigen needs e_i > 0 and distinct a_i")
     return E
+
+
+def truth_general(dt, rho_g, rho_d, t_stop):
+    """exp(dt K) of any valid cell (long double): the eigen-decomposition
+    with decoupled (t = inf), dust-free (rho_d = 0) and equal-a species split
+    off in closed form."""
+    lib = _load()
+    rho_d = _f64(rho_d)
+    t_stop = _f64(t_stop)
+    N = rho_d.size
+    E = np.zeros((N + 1, N + 1))
+    rc = lib.truth_expm_general(N, float(dt), float(rho_g), _ptr(rho_d),
+                                _ptr(t_stop), _ptr(E))
+    if rc != 0:
+        raise ValueError("truth_expm_general: invalid cell")
+    return E
+
+
+def truth_apply(rho_g, rho_d, t_stop, v, dt):
+    """The exact v' = exp(dt K) v for every cell of an SoA grid (long-double
+    truth_general); NaN on cells with invalid inputs."""
+    lib = _load()
+    rho_g, rho_d, t_stop, v = (_f64(x) for x in (rho_g, rho_d, t_stop, v))
+    D, n, C = v.shape
+    assert rho_d.shape == (n - 1, C) and t_stop.shape == (n - 1, C) and rho_g.shape == (C,)
+    out = np.empty_like(v)
+    if C:
+        lib.truth_apply_cells(C, n - 1, D, C, float(dt), _ptr(rho_g), _ptr(rho_d),
+                              _ptr(t_stop), _ptr(v), _ptr(out))
+    return out
 
 
 def truth_taylor(A, terms=200):

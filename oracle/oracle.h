@@ -59,5 +59,10 @@ int orc_rk1_cells(int64_t C, int N, int D, int64_t ld, double dt,
 int truth_expm_eigen(int N, double dt, double rho_g, const double *rho_d,
                      const double *t_stop, double *E);
 int truth_expm_taylor(int n, const double *A, int terms, double *E);
+int truth_expm_general(int N, double dt, double rho_g, const double *rho_d,
+                       const double *t_stop, double *E);
+int truth_apply_cells(int64_t C, int N, int D, int64_t ld, double dt,
+                      const double *rho_g, const double *rho_d,
+                      const double *t_stop, const double *v_in, double *v_out);
 
 #endif

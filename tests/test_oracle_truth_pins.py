@@ -1,0 +1,167 @@
+"""Pins of the general long-double truth (oracle/truth.c, truth_expm_general):
+exp(dt K) for cells with decoupled species (t = inf), dust-free species
+(rho_d = 0) and equal stopping times, which the plain eigen-decomposition
+cannot take.  The truth is what the GPU parity tests measure every cell
+against, so it is pinned to things that do not share its derivation:
+
+* multiprecision expm (mpmath, 40-60 digits) of dt K written out from the
+  drag ODE of Sect. 2.2 (dv_i/dt = -(v_i - v_g)/t_i, dv_g/dt =
+  sum (rho_i/rho_g)(v_i - v_g)/t_i) on small degenerate cells, also stiff
+  ones;
+* the eigen truth itself on cells where both apply (same bits expected);
+* the semigroup law E(dt1 + dt2) = E(dt1) E(dt2), row sums E 1 = 1 and
+  momentum rho^T E = rho^T on stiff degenerate cells;
+* continuity: e_i -> 0 and a_i -> a_j limits taken through the eigen truth.
+"""
+import numpy as np
+import pytest
+
+mp = pytest.importorskip("mpmath").mp
+
+
+def mp_ode_expm(dt, rho_g, rho_d, t_stop, dps=40):
+    """exp(dt K) with K read off the drag ODE in velocity form."""
+    with mp.workdps(dps):
+        N = len(rho_d)
+        n = N + 1
+        K = mp.zeros(n, n)
+        for i in range(N):
+            inv_t = mp.mpf(0) if np.isinf(t_stop[i]) else 1 / mp.mpf(t_stop[i])
+            eps = mp.mpf(rho_d[i]) / mp.mpf(rho_g)
+            K[i + 1, i + 1] = -inv_t
+            K[i + 1, 0] = inv_t
+            K[0, i + 1] = eps * inv_t
+            K[0, 0] -= eps * inv_t
+        E = mp.expm(K * mp.mpf(dt))
+        return np.array([[float(E[j, k]) for k in range(n)] for j in range(n)])
+
+
+def _degenerate_cells(rng, count, t_range):
+    cells = []
+    for trial in range(count):
+        N = 1 + trial % 5
+        rg = rng.uniform(0.5, 2.0)
+        rd = 10 ** rng.uniform(-3, 1, N) * rg
+        ts = 10 ** rng.uniform(*t_range, N)
+        kind = trial % 4
+        if kind == 0:
+            rd[rng.integers(N)] = 0.0           # dust-free species
+        elif kind == 1:
+            ts[rng.integers(N)] = np.inf        # decoupled species
+        elif kind == 2 and N >= 2:
+            i, j = rng.choice(N, 2, replace=False)
+            ts[j] = ts[i]                       # equal stopping times
+        else:
+            rd[0] = 0.0
+            ts[-1] = np.inf
+            if N >= 3:
+                ts[1] = ts[0] if rd[1] > 0 else ts[1]
+        cells.append((rg, rd, ts))
+    return cells
+
+
+def test_general_truth_equals_eigen_truth_where_both_apply(orc):
+    from paper_2509_25347_amd import workloads as W
+    for name in ("n4_3d", "n16_stiff_3d"):
+        d = W.make(name, 32)
+        for c in range(32):
+            args = (1.0, d["rho_g"][c], d["rho_d"][:, c], d["t_stop"][:, c])
+            assert np.array_equal(orc.truth_general(*args), orc.truth_eigen(*args))
+
+
+def test_general_truth_matches_multiprecision_on_degenerate_cells(orc):
+    rng = np.random.default_rng(71)
+    for k, (rg, rd, ts) in enumerate(_degenerate_cells(rng, 24, (-1.5, 1.0))):
+        E = orc.truth_general(1.0, rg, rd, ts)
+        assert np.abs(E - mp_ode_expm(1.0, rg, rd, ts)).max() <= 4e-16, k
+
+
+def test_general_truth_matches_multiprecision_stiff_degenerate(orc):
+    """||dt K|| up to ~1e4: mpmath at 60 digits still resolves every entry."""
+    rng = np.random.default_rng(72)
+    for k, (rg, rd, ts) in enumerate(_degenerate_cells(rng, 12, (-4.0, 1.0))):
+        E = orc.truth_general(1.0, rg, rd, ts)
+        assert np.abs(E - mp_ode_expm(1.0, rg, rd, ts, dps=60)).max() <= 1e-15, k
+
+
+def test_general_truth_only_degenerate_species(orc):
+    """No species that back-reacts: the gas stays put and every dust-free
+    species relaxes to it, v_i' = v_g + (v_i - v_g) e^{-a_i}; decoupled
+    species keep their velocity."""
+    rg, rd, ts = 1.3, np.array([0.0, 0.0, 2.0]), np.array([0.25, 4.0, np.inf])
+    E = orc.truth_general(1.0, rg, rd, ts)
+    ref = np.eye(4)
+    for i, t in enumerate(ts[:2]):
+        ref[i + 1, i + 1] = np.exp(-1.0 / t)
+        ref[i + 1, 0] = -np.expm1(-1.0 / t)
+    assert np.abs(E - ref).max() <= 2e-16
+
+
+def test_general_truth_invariants_stiff_degenerate(orc):
+    rng = np.random.default_rng(73)
+    for k, (rg, rd, ts) in enumerate(_degenerate_cells(rng, 40, (-7.0, 2.0))):
+        E1 = orc.truth_general(0.375, rg, rd, ts)
+        E2 = orc.truth_general(0.625, rg, rd, ts)
+        E = orc.truth_general(1.0, rg, rd, ts)
+        rho = np.concatenate([[rg], rd])
+        assert np.abs(E.sum(axis=1) - 1).max() <= 1e-15, k
+        assert np.abs(rho @ E - rho).max() <= 1e-15 * rho.sum(), k
+        assert E.min() >= -1e-16, k
+        assert np.abs(E1 @ E2 - E).max() <= 2e-15, k
+
+
+def test_general_truth_continuity_limits(orc):
+    """e_i -> 0 and a_i -> a_j taken through the eigen truth (which needs
+    e_i > 0 and distinct a_i) converge to the general truth's closed forms."""
+    rng = np.random.default_rng(74)
+    for trial in range(8):
+        N = 2 + trial % 3
+        rg = rng.uniform(0.5, 2.0)
+        rd = 10 ** rng.uniform(-2, 1, N) * rg
+        ts = 10 ** rng.uniform(-5, 1, N)
+        # dust-free limit
+        rd0 = rd.copy()
+        rd0[0] = 0.0
+        rdt = rd.copy()
+        rdt[0] = 1e-13 * rg
+        E0 = orc.truth_general(1.0, rg, rd0, ts)
+        Et = orc.truth_eigen(1.0, rg, rdt, ts)
+        assert np.abs(E0 - Et).max() <= 2e-12, trial
+        # equal-stopping-time limit (relative split 1e-9 of a)
+        ts1 = ts.copy()
+        ts1[1] = ts1[0]
+        ts2 = ts1.copy()
+        ts2[1] = ts1[0] * (1 + 1e-9)
+        E1 = orc.truth_general(1.0, rg, rd, ts1)
+        E2 = orc.truth_eigen(1.0, rg, rd, ts2)
+        assert np.abs(E1 - E2).max() <= 1e-7 * max(1.0, 1.0 / ts1[0]), trial
+
+
+def test_general_truth_rejects_invalid_cells(orc):
+    ok = (1.0, np.array([0.5]), np.array([0.1]))
+    orc.truth_general(1.0, *ok)
+    for rg, rd, ts in ((0.0, [0.5], [0.1]), (1.0, [-0.5], [0.1]), (1.0, [0.5], [0.0]),
+                       (1.0, [np.nan], [0.1]), (1.0, [0.5], [np.nan])):
+        with pytest.raises(ValueError):
+            orc.truth_general(1.0, rg, np.array(rd), np.array(ts))
+    with pytest.raises(ValueError):
+        orc.truth_general(-1.0, *ok)
+    assert np.array_equal(orc.truth_general(0.0, 1.0, np.array([0.5, 0.0]),
+                                            np.array([0.1, np.inf])), np.eye(3))
+
+
+def test_truth_apply_grid(orc):
+    from paper_2509_25347_amd import workloads as W
+    d = W.make("n8_adjoint_3d", 40)
+    d["t_stop"][2, 5] = np.inf
+    d["rho_d"][3, 7] = 0.0
+    d["rho_g"][9] = -1.0
+    d["v"][1, 4, 11] = np.nan
+    out = orc.truth_apply(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"])
+    for c in range(40):
+        if c in (9, 11):
+            assert np.isnan(out[..., c]).all() if c == 9 else np.isnan(out[1, :, c]).all()
+            continue
+        E = orc.truth_general(d["dt"], d["rho_g"][c], d["rho_d"][:, c], d["t_stop"][:, c])
+        ref = np.einsum("jk,dk->dj", E, d["v"][:, :, c])
+        assert np.abs(out[..., c] - ref).max() <= 1e-15 * np.abs(d["v"][..., c]).max(), c
