@@ -45,22 +45,27 @@ def _require(t, name):
 
 
 def _ld_of(t, rows_dims, name):
-    """Leading dimension of an SoA array whose last axis is the cell axis."""
+    """Leading dimension of an SoA array whose last axis is the cell axis:
+    the common spacing of its rows, which must be at least the row length
+    (expand()ed or overlapping views, whose rows share storage, are refused:
+    the library would read past their storage)."""
     st, sh = t.stride(), t.shape
     if st[-1] != 1:
         raise ValueError(f"{name}: the cell axis must be contiguous")
-    rows = 1
-    for n in sh[:-1]:
-        rows *= n
-    if rows <= 1:
-        return None  # one row (rho_g; rho_d at N = 1): its row stride is never used
-    ld = st[-2]
-    # all rows equally spaced by ld
-    exp = 1
+    ld, exp = None, 1
     for ax in range(len(sh) - 2, -1, -1):
-        if sh[ax] > 1 and st[ax] != ld * exp:
-            raise ValueError(f"{name}: rows must be equally spaced (stride ld)")
+        if sh[ax] > 1:
+            if ld is None:
+                if st[ax] % exp:
+                    raise ValueError(f"{name}: rows must be equally spaced (stride ld)")
+                ld = st[ax] // exp
+            elif st[ax] != ld * exp:
+                raise ValueError(f"{name}: rows must be equally spaced (stride ld)")
         exp *= sh[ax]
+    if ld is None:
+        return None  # one row (rho_g; rho_d at N = 1): its row stride is never used
+    if ld < sh[-1]:
+        raise ValueError(f"{name}: rows overlap (row stride {ld} below the {sh[-1]} cells)")
     return ld
 
 
@@ -226,7 +231,9 @@ class DragExpm(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_out):
-        rho_g, rho_d, t_stop, v = ctx.saved_tensors
+        # the fused adjoint takes contiguous arrays; the forward also accepts
+        # views with a padded leading dimension
+        rho_g, rho_d, t_stop, v = (x.contiguous() for x in ctx.saved_tensors)
         _, g_v, g_logt, g_rho, g_rho_g, g_t = expm_apply_backward(
             rho_g, rho_d, t_stop, v, grad_out.contiguous(), ctx.dt, ctx.k_max, ctx.option,
             want_v_out=False, want_grad_t=True)

@@ -59,3 +59,53 @@ def test_shapes_share_one_leading_dimension(monkeypatch):
         ops._shapes(rho_g, rho_d4, t4, v4)
     t4p = torch.zeros((4, ld), dtype=torch.float64)[:, :C]
     assert ops._shapes(rho_g, rho_d4, t4p, v4) == (C, 4, 3, ld)
+
+
+def test_overlapping_rows_are_refused(monkeypatch):
+    """An expand()ed view (row stride 0) or rows closer than the cell count
+    share storage; the library would read D (N+1) ld doubles from it."""
+    from paper_2509_25347_amd import ops
+    monkeypatch.setattr(ops, "_require", lambda t, name: None)
+    v = torch.zeros(100, dtype=torch.float64).view(1, 1, 100).expand(3, 2, 100)
+    with pytest.raises(ValueError):
+        ops._ld_of(v, 2, "v")
+    base = torch.zeros(1000, dtype=torch.float64)
+    close = base.as_strided((3, 2, 100), (100, 50, 1))  # rows 50 apart, 100 cells each
+    with pytest.raises(ValueError):
+        ops._ld_of(close, 2, "v")
+    rho_d = base.as_strided((4, 100), (60, 1))
+    with pytest.raises(ValueError):
+        ops._ld_of(rho_d, 1, "rho_d")
+    rho_g = torch.zeros(100, dtype=torch.float64)
+    t = torch.zeros((1, 100), dtype=torch.float64)
+    rd = torch.zeros((1, 100), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        ops._shapes(rho_g, rd, t, v)
+
+
+def test_autograd_backward_hands_contiguous_inputs(monkeypatch):
+    """The forward accepts padded views; the fused adjoint takes contiguous
+    arrays, so DragExpm.backward passes contiguous copies."""
+    from paper_2509_25347_amd import ops
+    C, ld, N, D = 50, 64, 3, 2
+    saved = (torch.zeros(C, dtype=torch.float64),
+             torch.zeros((N, ld), dtype=torch.float64)[:, :C],
+             torch.ones((N, ld), dtype=torch.float64)[:, :C],
+             torch.zeros((D, N + 1, ld), dtype=torch.float64)[..., :C])
+    seen = {}
+
+    def fake_backward(rho_g, rho_d, t_stop, v, grad_out, dt, k_max, option, **kw):
+        seen["contiguous"] = all(x.is_contiguous() for x in (rho_g, rho_d, t_stop, v, grad_out))
+        z = torch.zeros_like
+        return None, z(v), z(rho_d), z(rho_d), z(rho_g), z(t_stop)
+
+    monkeypatch.setattr(ops, "expm_apply_backward", fake_backward)
+
+    class Ctx:
+        saved_tensors = saved
+        dt, k_max, option = 1.0, 9, 2
+        needs_input_grad = (True, True, True, True, False, False, False)
+
+    grads = ops.DragExpm.backward(Ctx(), torch.zeros((D, N + 1, ld), dtype=torch.float64)[..., :C])
+    assert seen["contiguous"]
+    assert grads[3].shape == (D, N + 1, C)
