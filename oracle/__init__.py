@@ -91,6 +91,8 @@ def _load():
     lib.truth_expm_general.restype = i
     lib.truth_apply_cells.argtypes = [i64, i, i, i64, d, vp, vp, vp, vp, vp]
     lib.truth_apply_cells.restype = i
+    lib.truth_grad_cells.argtypes = [i64, i, i, i64, d] + [vp] * 9
+    lib.truth_grad_cells.restype = i
     _lib = lib
     return lib
 
@@ -270,6 +272,25 @@ def truth_apply(rho_g, rho_d, t_stop, v, dt):
         lib.truth_apply_cells(C, n - 1, D, C, float(dt), _ptr(rho_g), _ptr(rho_d),
                               _ptr(t_stop), _ptr(v), _ptr(out))
     return out
+
+
+def truth_grad(rho_g, rho_d, t_stop, v, w, dt):
+    """The exact gradient of L = sum w . exp(dt K) v per cell (long double,
+    Daleckii-Krein form in the eigenbasis): (g_v, g_logt, g_rho_d, g_rho_g);
+    NaN on cells the eigen-decomposition cannot take (a species with e_i = 0
+    or a_i = 0, equal a_i) or with invalid inputs."""
+    lib = _load()
+    rho_g, rho_d, t_stop, v, w = (_f64(x) for x in (rho_g, rho_d, t_stop, v, w))
+    D, n, C = v.shape
+    assert w.shape == v.shape and rho_d.shape == (n - 1, C) and t_stop.shape == (n - 1, C)
+    g_v = np.empty_like(v)
+    g_lt = np.empty((n - 1, C))
+    g_rd = np.empty((n - 1, C))
+    g_rg = np.empty(C)
+    if C:
+        lib.truth_grad_cells(C, n - 1, D, C, float(dt), _ptr(rho_g), _ptr(rho_d), _ptr(t_stop),
+                             _ptr(v), _ptr(w), _ptr(g_v), _ptr(g_lt), _ptr(g_rd), _ptr(g_rg))
+    return g_v, g_lt, g_rd, g_rg
 
 
 def truth_taylor(A, terms=200):

@@ -64,5 +64,9 @@ int truth_expm_general(int N, double dt, double rho_g, const double *rho_d,
 int truth_apply_cells(int64_t C, int N, int D, int64_t ld, double dt,
                       const double *rho_g, const double *rho_d,
                       const double *t_stop, const double *v_in, double *v_out);
+int truth_grad_cells(int64_t C, int N, int D, int64_t ld, double dt,
+                     const double *rho_g, const double *rho_d,
+                     const double *t_stop, const double *v_in, const double *w_in,
+                     double *g_v, double *g_logt, double *g_rho_d, double *g_rho_g);
 
 #endif

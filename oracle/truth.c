@@ -34,6 +34,18 @@
  *
  * truth_apply_cells -- v' = E v on an SoA grid with E from
  *   truth_expm_general; cells with invalid inputs get NaN.
+ *
+ * truth_grad_cells -- the exact gradient of L = sum_d w_d . (E v_d) with
+ *   respect to v, log t_i, rho_i and rho_g on an SoA grid.  dL/dA for
+ *   L = <G, exp(A)>, G = sum_d w_d v_d^T, is the Frechet derivative of the
+ *   exponential at A^T in the direction G; with A = W^-1 S W (S the
+ *   symmetrised matrix, W = diag(w)) it is W L_S[W^-1 G W] W^-1, where for
+ *   symmetric S = Q diag(lam) Q^T the derivative is the Daleckii-Krein form
+ *   L_S[X] = Q (Phi o (Q^T X Q)) Q^T with the divided differences
+ *   Phi_lm = (e^lam_l - e^lam_m) / (lam_l - lam_m) (e^lam_l on the
+ *   diagonal).  The chain rule through A00 = -sum e_i a_i, A0i = e_i a_i,
+ *   Ai0 = a_i, Aii = -a_i, a_i = dt / t_i, e_i = rho_i / rho_g follows.
+ *   Cells the eigen-decomposition cannot take (see truth_expm_eigen) get NaN.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -355,4 +367,112 @@ int truth_apply_cells(int64_t C, int N, int D, int64_t ld, double dt,
         bad += (rc != 0);
     }
     return bad;
+}
+
+/* e^x - e^y over x - y, without cancellation when x and y are close */
+static ld_t exp_divdiff(ld_t x, ld_t y)
+{
+    ld_t d = x - y;
+    if (d == 0.0L) return expl(y);
+    if (fabsl(d) > 0.5L) return (expl(x) - expl(y)) / d;
+    return expl(y) * (expm1l(d) / d);
+}
+
+int truth_grad_cells(int64_t C, int N, int D, int64_t ld, double dt,
+                     const double *rho_g, const double *rho_d,
+                     const double *t_stop, const double *v_in, const double *w_in,
+                     double *g_v, double *g_logt, double *g_rho_d, double *g_rho_g)
+{
+    const int n = N + 1;
+    if (C < 0 || N < 1 || n > ORC_NMAX || D < 1 || ld < C) return -1;
+    int bad_cells = 0;
+    for (int64_t c = 0; c < C; ++c) {
+        ld_t a[ORC_NMAX], e[ORC_NMAX];
+        int ok = (dt > 0) && isfinite(dt) && (rho_g[c] > 0) && isfinite(rho_g[c]);
+        for (int i = 0; i < N && ok; ++i) {
+            const double ts = t_stop[(size_t)i * ld + c], rd = rho_d[(size_t)i * ld + c];
+            a[i] = (ld_t)dt / (ld_t)ts;
+            e[i] = (ld_t)rd / (ld_t)rho_g[c];
+            ok = (ts > 0) && (rd > 0) && isfinite(rd) && (a[i] > 0) && isfinite((double)a[i]);
+        }
+        for (int i = 0; i < N && ok; ++i)
+            for (int j = 0; j < i && ok; ++j) ok = (a[i] != a[j]);
+        for (int d = 0; d < D && ok; ++d)
+            for (int j = 0; j < n && ok; ++j)
+                ok = isfinite(v_in[((size_t)d * n + j) * ld + c]) &&
+                     isfinite(w_in[((size_t)d * n + j) * ld + c]);
+        if (!ok) {
+            ++bad_cells;
+            for (int d = 0; d < D; ++d)
+                for (int j = 0; j < n; ++j) g_v[((size_t)d * n + j) * ld + c] = NAN;
+            for (int i = 0; i < N; ++i) {
+                g_logt[(size_t)i * ld + c] = NAN;
+                g_rho_d[(size_t)i * ld + c] = NAN;
+            }
+            g_rho_g[c] = NAN;
+            continue;
+        }
+        int orig[ORC_NMAX];
+        ld_t mu[ORC_NMAX], X[ORC_NMAX][ORC_NMAX], w[ORC_NMAX], lam[ORC_NMAX], el[ORC_NMAX];
+        arrow_modes(N, a, e, orig, mu, X, w);
+        for (int l = 0; l < n; ++l) {
+            lam[l] = (orig[l] < 0) ? 0.0L : -a[orig[l]] + mu[l];
+            el[l] = expl(lam[l]);
+        }
+        /* E (for dL/dv = E^T w) and G = sum_d w_d v_d^T */
+        ld_t E[ORC_NMAX][ORC_NMAX], G[ORC_NMAX][ORC_NMAX];
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                ld_t acc = 0.0L;
+                for (int l = 0; l < n; ++l) acc += X[j][l] * X[k][l] * el[l];
+                E[j][k] = acc * w[k] / w[j];
+                ld_t g = 0.0L;
+                for (int d = 0; d < D; ++d)
+                    g += (ld_t)w_in[((size_t)d * n + j) * ld + c] *
+                         (ld_t)v_in[((size_t)d * n + k) * ld + c];
+                G[j][k] = g;
+            }
+        for (int d = 0; d < D; ++d)
+            for (int k = 0; k < n; ++k) {
+                ld_t acc = 0.0L;
+                for (int j = 0; j < n; ++j) acc += E[j][k] * (ld_t)w_in[((size_t)d * n + j) * ld + c];
+                g_v[((size_t)d * n + k) * ld + c] = (double)acc;
+            }
+        /* H = X^T (W^-1 G W) X, then Phi o H, then back: L = X (Phi o H) X^T */
+        ld_t T1[ORC_NMAX][ORC_NMAX], H[ORC_NMAX][ORC_NMAX], L[ORC_NMAX][ORC_NMAX];
+        for (int j = 0; j < n; ++j)
+            for (int m = 0; m < n; ++m) {
+                ld_t acc = 0.0L;
+                for (int k = 0; k < n; ++k) acc += (G[j][k] * w[k] / w[j]) * X[k][m];
+                T1[j][m] = acc;
+            }
+        for (int l = 0; l < n; ++l)
+            for (int m = 0; m < n; ++m) {
+                ld_t acc = 0.0L;
+                for (int j = 0; j < n; ++j) acc += X[j][l] * T1[j][m];
+                H[l][m] = acc * exp_divdiff(lam[l], lam[m]);
+            }
+        for (int l = 0; l < n; ++l)
+            for (int k = 0; k < n; ++k) {
+                ld_t acc = 0.0L;
+                for (int m = 0; m < n; ++m) acc += H[l][m] * X[k][m];
+                T1[l][k] = acc;
+            }
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                ld_t acc = 0.0L;
+                for (int l = 0; l < n; ++l) acc += X[j][l] * T1[l][k];
+                L[j][k] = acc * w[j] / w[k]; /* Abar */
+            }
+        ld_t grg = 0.0L;
+        for (int i = 0; i < N; ++i) {
+            const ld_t ga = L[0][i + 1] * e[i] + L[i + 1][0] - L[i + 1][i + 1] - L[0][0] * e[i];
+            const ld_t ge = a[i] * (L[0][i + 1] - L[0][0]);
+            g_logt[(size_t)i * ld + c] = (double)(-a[i] * ga);
+            g_rho_d[(size_t)i * ld + c] = (double)(ge / (ld_t)rho_g[c]);
+            grg -= ge * e[i] / (ld_t)rho_g[c];
+        }
+        g_rho_g[c] = (double)grg;
+    }
+    return bad_cells;
 }

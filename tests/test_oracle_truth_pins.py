@@ -1,8 +1,9 @@
-"""Pins of the general long-double truth (oracle/truth.c, truth_expm_general):
-exp(dt K) for cells with decoupled species (t = inf), dust-free species
-(rho_d = 0) and equal stopping times, which the plain eigen-decomposition
-cannot take.  The truth is what the GPU parity tests measure every cell
-against, so it is pinned to things that do not share its derivation:
+"""Pins of the long-double truths in oracle/truth.c that the GPU parity tests
+measure every cell against: truth_expm_general, exp(dt K) also for cells
+with decoupled species (t = inf), dust-free species (rho_d = 0) and equal
+stopping times, which the plain eigen-decomposition cannot take; and
+truth_grad_cells, the exact gradient of L = sum w . exp(dt K) v.  Each is
+pinned to things that do not share its derivation:
 
 * multiprecision expm (mpmath, 40-60 digits) of dt K written out from the
   drag ODE of Sect. 2.2 (dv_i/dt = -(v_i - v_g)/t_i, dv_g/dt =
@@ -11,7 +12,10 @@ against, so it is pinned to things that do not share its derivation:
 * the eigen truth itself on cells where both apply (same bits expected);
 * the semigroup law E(dt1 + dt2) = E(dt1) E(dt2), row sums E 1 = 1 and
   momentum rho^T E = rho^T on stiff degenerate cells;
-* continuity: e_i -> 0 and a_i -> a_j limits taken through the eigen truth.
+* continuity: e_i -> 0 and a_i -> a_j limits taken through the eigen truth;
+* for the gradient: central differences of a multiprecision forward (the
+  stored fixture, and stiff cells with a tiny step at 40 digits), and the
+  sum rules of E 1 = 1 and rho^T E = rho^T.
 """
 import numpy as np
 import pytest
@@ -165,3 +169,78 @@ def test_truth_apply_grid(orc):
         E = orc.truth_general(d["dt"], d["rho_g"][c], d["rho_d"][:, c], d["t_stop"][:, c])
         ref = np.einsum("jk,dk->dj", E, d["v"][:, :, c])
         assert np.abs(out[..., c] - ref).max() <= 1e-15 * np.abs(d["v"][..., c]).max(), c
+
+
+# ---- the exact gradient (truth_grad_cells) --------------------------------------
+
+def _group_rel(got, ref, floor=None):
+    g = np.moveaxis(np.asarray(got), -1, 0).reshape(np.shape(got)[-1], -1)
+    r = np.moveaxis(np.asarray(ref), -1, 0).reshape(np.shape(ref)[-1], -1)
+    sc = np.abs(r).max(axis=1)
+    if floor is not None:
+        sc = np.maximum(sc, floor)
+    return np.abs(g - r).max(axis=1) / sc
+
+
+@pytest.mark.parametrize("N", [5, 8, 10, 12])
+def test_exact_gradient_matches_stored_multiprecision_differences(orc, N):
+    from fd_fixture import load
+    d, fd = load(N)
+    g_v, g_lt, g_rd, g_rg = orc.truth_grad(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["w"],
+                                           d["dt"])
+    assert _group_rel(g_lt, fd["g_logt"]).max() <= 2e-12
+    assert _group_rel(g_rd, fd["g_rho_d"]).max() <= 2e-12
+    assert _group_rel(g_v, fd["g_v"]).max() <= 2e-12
+    assert (np.abs(g_rg - fd["g_rho_g"]) / np.abs(fd["g_rho_g"])).max() <= 2e-12
+
+
+def test_exact_gradient_matches_multiprecision_differences_stiff(orc):
+    """Stiff small cells (||dt K|| up to ~1e5): central differences with a
+    tiny step of a 40-digit forward."""
+    from oracle import mpfd
+    rng = np.random.default_rng(75)
+    for trial in range(6):
+        N = 2 + trial % 2
+        rg = rng.uniform(0.5, 2.0)
+        rd = 10 ** rng.uniform(-2, 0.5, N) * rg
+        ts = np.sort(10 ** rng.uniform(-5, 1, N))
+        v = rng.standard_normal((2, N + 1))
+        w = rng.standard_normal((2, N + 1))
+        fd = mpfd.fd_gradients(rg, rd, ts, v, w, dt=1.0, h=1e-9, dps=40)
+        g_v, g_lt, g_rd, g_rg = orc.truth_grad(np.array([rg]), rd[:, None], ts[:, None],
+                                               v[:, :, None], w[:, :, None], 1.0)
+        S = np.abs(w).max() * np.abs(v).max() * 2
+        assert np.abs(g_lt[:, 0] - fd["g_logt"]).max() <= 1e-12 * max(np.abs(fd["g_logt"]).max(), S)
+        assert np.abs(g_rd[:, 0] - fd["g_rho_d"]).max() <= 1e-12 * max(np.abs(fd["g_rho_d"]).max(), S / rg)
+        assert np.abs(g_v[:, :, 0] - fd["g_v"]).max() <= 1e-12 * np.abs(fd["g_v"]).max()
+        assert abs(g_rg[0] - fd["g_rho_g"]) <= 1e-12 * max(abs(fd["g_rho_g"]), S / rg)
+
+
+def test_exact_gradient_sum_rules_stiff(orc):
+    """E 1 = 1 for every parameter value (a uniform v has no log t or rho
+    gradient) and rho^T E = rho^T (weights w = rho have no log t gradient),
+    to the long-double rounding of the chain rule (a_i up to 1e6 times the
+    entries of dL/dA)."""
+    from paper_2509_25347_amd import workloads as W
+    d = W.make("n16_stiff_3d", 16)
+    rng = np.random.default_rng(76)
+    w = rng.standard_normal(d["v"].shape)
+    vu = np.repeat(rng.standard_normal((3, 1, 16)), 17, axis=1)
+    g_v, g_lt, g_rd, g_rg = orc.truth_grad(d["rho_g"], d["rho_d"], d["t_stop"], vu, w, 1.0)
+    ref = orc.truth_grad(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], w, 1.0)
+    assert np.abs(g_lt).max() <= 1e-12 * np.abs(ref[1]).max()
+    assert np.abs(g_rd).max() <= 1e-12 * np.abs(ref[2]).max()
+    rho = np.concatenate([d["rho_g"][None], d["rho_d"]])
+    wr = np.repeat(rho[None], 3, axis=0)
+    g_v, g_lt, _, _ = orc.truth_grad(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], wr, 1.0)
+    assert np.abs(g_lt).max() <= 1e-12 * np.abs(ref[1]).max() * rho.max()
+    assert np.abs(g_v - wr).max() <= 1e-15 * rho.max()
+
+
+def test_exact_gradient_refuses_degenerate_cells(orc):
+    d = dict(rho_g=np.array([1.0, 1.0, 1.0]), rho_d=np.array([[0.5, 0.0, 0.5], [0.2, 0.2, 0.2]]),
+             t_stop=np.array([[0.1, 0.1, np.inf], [0.3, 0.3, 0.3]]))
+    v = np.ones((1, 3, 3))
+    g_v, g_lt, g_rd, g_rg = orc.truth_grad(d["rho_g"], d["rho_d"], d["t_stop"], v, v, 1.0)
+    assert np.isfinite(g_lt[:, 0]).all()
+    assert np.isnan(g_lt[:, 1:]).all() and np.isnan(g_rg[1:]).all()
