@@ -373,6 +373,30 @@ def _err_stats(got, ref, v):
             "median": float(np.median(e))}
 
 
+def _exact_stats(d, got, ref, dt):
+    """Errors against the exact exponential (the oracle's long-double truth,
+    no scaling and squaring) on the oracle's sample: the GPU's, the
+    oracle's, and the GPU's excess over the oracle's own error per cell."""
+    import oracle
+    C = ref.shape[-1]
+    v = d["v"][..., :C]
+    tr = oracle.truth_apply(d["rho_g"][:C], d["rho_d"][:, :C], d["t_stop"][:, :C], v, dt)
+    scale = np.abs(v).max(axis=1)
+    scale = np.where(scale == 0, 1.0, scale)
+
+    def per_cell(x, y):
+        return (np.abs(x - y).max(axis=1) / scale).max(axis=0)
+
+    e_gx, e_ox, e_go = per_cell(got, tr), per_cell(ref, tr), per_cell(got, ref)
+
+    def stats(e):
+        return {"max": float(e.max()), "p99.9": float(np.quantile(e, 0.999)),
+                "median": float(np.median(e))}
+
+    return {"gpu_vs_exact": stats(e_gx), "oracle_vs_exact": stats(e_ox),
+            "max_gpu_vs_oracle_minus_oracle_vs_exact": float((e_go - e_ox).max())}
+
+
 def config_report(torch, ops, _lib, workloads, dev):
     """All five workload configurations on one GPU, with the oracle timed
     beside the GPU on a bounded sample of the same cells (single thread and
@@ -397,6 +421,7 @@ def config_report(torch, ops, _lib, workloads, dev):
                "fp64_frac": f_alg / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                "hbm_frac": algorithmic_bytes(C, N, D) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                "err_vs_oracle": _err_stats(got[..., :ref.shape[-1]], ref, d["v"][..., :ref.shape[-1]]),
+               "err_vs_exact": _exact_stats(d, got[..., :ref.shape[-1]], ref, d["dt"]),
                "oracle_sample": int(ref.shape[-1]), "oracle_1core_cells_per_s": r1,
                "oracle_all_cores_cells_per_s": rp}
         if cfg == 1:  # launch-bound: the device time per launch, from graph replays
@@ -445,18 +470,25 @@ def config_report(torch, ops, _lib, workloads, dev):
     with ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(run, sample))
     tp = time.perf_counter() - t0
-    errs = []
+    errs, ex = [], []
     for b, (blk, r) in enumerate(zip(sample, refs)):
         got = plan.block_view(vo, b).cpu().numpy()
         scale = np.abs(blk["v"]).max(axis=1)
         errs.append((np.abs(got - r[0]).max(axis=1) / np.where(scale == 0, 1, scale)).max(axis=0))
+        ex.append(_exact_stats(blk, got, r[0], batch["dt"]))
     e = np.concatenate(errs)
+    exact = {k: {s: max(x[k][s] for x in ex) for s in ("max", "p99.9")}
+             for k in ("gpu_vs_exact", "oracle_vs_exact")}
+    exact["note"] = "max over the 32 blocks of each block's max and p99.9"
+    exact["max_gpu_vs_oracle_minus_oracle_vs_exact"] = max(
+        x["max_gpu_vs_oracle_minus_oracle_vs_exact"] for x in ex)
     plan.close()
     out["config4"] = {"workload": "batched 4096 x 512, N_b ~ U{1..16}", "cells": cells, "ms": ms,
                       "cells_per_s": cells / (ms * 1e-3),
                       "fp64_frac": f_alg / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                       "err_vs_oracle": {"max": float(e.max()), "p99.9": float(np.quantile(e, 0.999)),
                                         "median": float(np.median(e))},
+                      "err_vs_exact": exact,
                       "oracle_sample": int(e.size),
                       "oracle_1core_cells_per_s": e.size / t1,
                       "oracle_all_cores_cells_per_s": e.size / tp}

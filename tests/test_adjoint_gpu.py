@@ -3,21 +3,29 @@
 Gradients of L = sum w . v' with respect to v, log t_i, rho_i and rho_g.
 References: the oracle's reverse-mode gradient (a different derivation: it
 stores the chain and runs it backwards through the paper's dense steps),
-central finite differences of the GPU forward, and sum rules.  Per cell and
-per group (v, log t, rho_d, rho_g) the error is
-    max |g - g_ref| / max(max |g_ref|, S),
+central differences of a multiprecision forward (tests/golden/
+fd_gradients.json), central differences of the GPU forward, and sum rules.
+Per cell and per group (v, log t, rho_d, rho_g) the error is
+    e = max |g - g_ref| / max(max |g_ref|, S),
 with S = sum_c ||w_c||_inf ||v_c||_inf the natural size of L's sensitivities
 (divided by rho_g for the density gradients): where every mode of a cell has
 decayed, dL/dlog t is ~1e-16 and only its absolute error is meaningful.
+e <= 1e-10 against the exact gradient (long double, oracle/truth.c), and
+e <= 1e-10 + e(oracle, exact) against the oracle's (tests/bars.py).
+Against the multiprecision differences: max |g - g_fd| / max |g_fd| <= 1e-8
+per cell and group, for every adjoint kernel.  The fused forward v' meets the
+forward's parity bars (tests/bars.py).
 """
 import numpy as np
 import pytest
 
 from paper_2509_25347_amd import workloads as W
+from bars import GRAD_TOL, check_forward, check_gradients, group_err, sens_scale
+from fd_fixture import group_rel_err
+from fd_fixture import load as load_fd
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-U = 2.0 ** -53
 
 
 @pytest.fixture(scope="module")
@@ -45,22 +53,6 @@ def _weights(d, seed=0):
     return d
 
 
-def sens_scale(d):
-    """S per cell: sum over components of ||w_c||_inf ||v_c||_inf."""
-    return (np.abs(d["w"]).max(axis=1) * np.abs(d["v"]).max(axis=1)).sum(axis=0)
-
-
-def group_err(got, ref, floor=None, cell_axis=-1):
-    """max over the group of |got - ref| / max(max |ref|, floor), per cell."""
-    g = np.moveaxis(got, cell_axis, 0).reshape(got.shape[cell_axis], -1)
-    r = np.moveaxis(ref, cell_axis, 0).reshape(ref.shape[cell_axis], -1)
-    scale = np.abs(r).max(axis=1)
-    if floor is not None:
-        scale = np.maximum(scale, floor)
-    scale = np.where(scale == 0, 1.0, scale)
-    return np.abs(g - r).max(axis=1) / scale
-
-
 def gpu_backward(ops, d, dev, **kw):
     T = _to(d, dev)
     res = ops.expm_apply_backward(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], T["w"], d["dt"],
@@ -70,18 +62,15 @@ def gpu_backward(ops, d, dev, **kw):
 
 
 def check_vs_oracle(orc, d, got, tol, label):
+    """The fused forward against the forward's bars, the gradients against
+    the exact gradient and the oracle's (tests/bars.py), and dL/dt against
+    dL/dlog t / t."""
     v_out, g_v, g_logt, g_rho, g_rho_g, g_t = got
     ro = orc.grad_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["w"], d["dt"])
-    rv, rgv, rlt, rrho, rrg, st = ro
-    assert st == 0
-    S = sens_scale(d)
-    Sr = S / d["rho_g"]
-    errs = {"v_out": group_err(v_out, rv), "g_v": group_err(g_v, rgv),
-            "g_logt": group_err(g_logt, rlt, S), "g_rho_d": group_err(g_rho, rrho, Sr),
-            "g_rho_g": np.abs(g_rho_g - rrg) / np.maximum(np.abs(rrg), Sr)}
-    for k, e in errs.items():
-        assert np.isfinite(e).all(), (label, k)
-        assert e.max() <= tol, (label, k, e.max(), int(e.argmax()))
+    assert ro[-1] == 0
+    check_forward(orc, v_out, ro[0], d, (label, "fused forward"))
+    errs = check_gradients(orc, d, (g_v, g_logt, g_rho, g_rho_g), label, tol,
+                           oracle_grads=ro[1:5])
     np.testing.assert_allclose(g_t, g_logt / d["t_stop"], rtol=1e-15, atol=0)
     return errs
 
@@ -91,7 +80,7 @@ def check_vs_oracle(orc, d, got, tol, label):
 def test_backward_vs_oracle(ops, dev, orc, name, cells):
     d = _weights(W.make(name, cells))
     got = gpu_backward(ops, d, dev)
-    check_vs_oracle(orc, d, got, 1e-9, name)
+    check_vs_oracle(orc, d, got, GRAD_TOL, name)
 
 
 @pytest.mark.parametrize("N", list(range(1, 17)))
@@ -103,7 +92,7 @@ def test_backward_every_n_both_mappings(ops, dev, orc, N):
         for mp in maps:
             _lib.set_mapping(N, mp)
             got = gpu_backward(ops, d, dev)
-            check_vs_oracle(orc, d, got, 1e-9, f"N={N} map={mp}")
+            check_vs_oracle(orc, d, got, GRAD_TOL, f"N={N} map={mp}")
     finally:
         _lib.set_mapping(N, _lib.MAP_AUTO)
 
@@ -128,15 +117,56 @@ FD_CASES = {
 }
 
 
+MPFD_CASES = {
+    # name: (species N of the stored cells, mapping override or None, kernel expected)
+    "one_lane_n5": (5, None, "lane"),
+    "pair_n8": (8, None, "pair"),
+    "mfma_block_n8": (8, 2, "mfma block form"),
+    "pair_n10": (10, None, "pair"),
+    "mfma_n12": (12, None, "mfma"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(MPFD_CASES))
+def test_backward_vs_multiprecision_fd(ops, dev, orc, case):
+    """The adjoint against central differences (h = 1e-6) of a multiprecision
+    forward (mpmath expm at 30 digits; the stored 8 cells per N of the
+    N = 8 adjoint workload's recipe): 1e-8 of each group's largest entry,
+    per cell, for every adjoint kernel (one lane per cell, two lanes per cell
+    at N = 8 and 10, the MFMA block form, the MFMA kernel above 10); and
+    the oracle's gradient on the same cells to 1e-10."""
+    from paper_2509_25347_amd import _lib
+    N, mapping, _ = MPFD_CASES[case]
+    d, fd = load_fd(N)
+    if mapping is not None:
+        _lib.set_mapping(N, mapping)
+    try:
+        print(f"adjoint vs multiprecision differences: {case} ({MPFD_CASES[case][2]})", flush=True)
+        got = gpu_backward(ops, d, dev)
+    finally:
+        if mapping is not None:
+            _lib.set_mapping(N, _lib.MAP_AUTO)
+    v_out, g_v, g_logt, g_rho, g_rho_g, g_t = got
+    errs = {"g_logt": group_rel_err(g_logt, fd["g_logt"]),
+            "g_rho_d": group_rel_err(g_rho, fd["g_rho_d"]),
+            "g_v": group_rel_err(g_v, fd["g_v"]),
+            "g_rho_g": np.abs(g_rho_g - fd["g_rho_g"]) / np.abs(fd["g_rho_g"])}
+    for k, e in errs.items():
+        assert np.isfinite(e).all() and e.max() <= 1e-8, (case, k, e)
+    print(case, {k: float(e.max()) for k, e in errs.items()})
+    check_vs_oracle(orc, d, got, GRAD_TOL, case)
+
+
 @pytest.mark.parametrize("case", sorted(FD_CASES))
 def test_backward_vs_finite_differences(ops, dev, case):
-    """Central differences of the GPU forward with h = 1e-6 in each
-    parameter's natural scale: additive in log t_i and v, steps of h rho_g in
-    rho_i (the scale of e_i = rho_i / rho_g; a step relative to a small rho_i
-    would divide the forward's rounding noise by a tiny number) and relative
-    in rho_g.  Agreement to 1e-7 of the group scale.  One case per adjoint
-    kernel: one lane per cell, two lanes per cell (the N = 8 default, and
-    N = 10), the MFMA block form and the MFMA kernel for N > 10."""
+    """Central differences of the GPU's own FP64 forward with h = 1e-6 in
+    each parameter's natural scale: additive in log t_i and v, steps of
+    h rho_g in rho_i (the scale of e_i = rho_i / rho_g; a step relative to a
+    small rho_i would divide the forward's rounding noise by a tiny number)
+    and relative in rho_g.  The forward's rounding noise (~1e-15) over the
+    step makes these differences themselves uncertain to a few 1e-8, so the
+    bar is 1e-7 of the group scale; the 1e-8 check is the multiprecision one
+    above.  One case per adjoint kernel."""
     from paper_2509_25347_amd import _lib
     make, n_map, mapping = FD_CASES[case]
     if n_map is not None:
@@ -256,6 +286,30 @@ def test_backward_short_quads(ops, dev, orc, N):
         for C in (1, 3, 5, 7):
             d = _weights(W.make_stiff(N, C), seed=C)
             got = gpu_backward(ops, d, dev)
-            check_vs_oracle(orc, d, got, 1e-9, f"N={N} C={C}")
+            check_vs_oracle(orc, d, got, GRAD_TOL, f"N={N} C={C}")
     finally:
         _lib.set_mapping(N, _lib.MAP_AUTO)
+
+
+def test_autograd_with_padded_inputs(ops, dev):
+    """DragExpm's forward takes views with a padded leading dimension; its
+    backward hands the fused adjoint contiguous copies: the gradients equal
+    those of contiguous inputs bit for bit."""
+    d = _weights(W.make("n4_3d", 300), seed=11)
+    C, ld = 300, 320
+    T = _to(d, dev)
+
+    def padded(x):
+        p = torch.full(x.shape[:-1] + (ld,), float("nan"), dtype=x.dtype, device=dev)
+        p[..., :C] = x
+        return p[..., :C]
+
+    grads = []
+    for make in (lambda x: x.clone(), padded):
+        leaves = {k: make(T[k]).requires_grad_(True) for k in ("rho_d", "t_stop", "v")}
+        rg = T["rho_g"].clone().requires_grad_(True)
+        out = ops.drag_expm(rg, leaves["rho_d"], leaves["t_stop"], leaves["v"], d["dt"])
+        (out * T["w"]).sum().backward()
+        grads.append([rg.grad] + [leaves[k].grad for k in ("rho_d", "t_stop", "v")])
+    for a, b in zip(*grads):
+        assert torch.equal(a, b)
