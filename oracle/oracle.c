@@ -112,52 +112,53 @@ double orc_taylor_coef(int i)
 }
 
 /* ---- Alg. 1: choice of (k*, m*, s*) --------------------------------------- */
-/* Appendix B, "First modification", Alg. 1 with options 0, 1, 2 and a cap K on
- * the number of products of the polynomial stage.  nrm must be finite. */
+/* Appendix B, "First modification" (Alg. 1 with options 0, 1, 2 and a cap K
+ * on the products of the polynomial stage), stated through its cost model:
+ * row k of Table B.1 costs Pi_{m_k} = k products, each squaring one more, and
+ * row k is admissible for a scaling 2^-s when ||A|| / 2^s <= theta_{m_k}
+ * (eq. B8).
+ *   Base choice: without scaling, the cheapest admissible row; when no row
+ *   up to K is, row K with s-hat, the fewest squarings that make it
+ *   admissible.
+ *   Trades: the options then replace (k, s) by (k + dk, s + ds) if that pair
+ *   is admissible, trying in order one product fewer at the same s
+ *   (option >= 1, rows 7..9) and two or three polynomial products for one or
+ *   two squarings, the same total cost at a lower degree (option 2, rows
+ *   8..9 and row 9).  The first admissible trade is taken.
+ * The comparisons are exact: ||A|| 2^-s is an exact scaling of a double.
+ * nrm must be finite. */
+typedef struct {
+    int dk, ds, min_option, k_lo, k_hi;
+} select_trade;
+
+static const select_trade SELECT_TRADES[3] = {
+    {-1, 0, 1, 7, 9},
+    {-2, 1, 2, 8, 9},
+    {-3, 2, 2, 9, 9},
+};
+
 void orc_select(double nrm, int K, int option, int *kout, int *mout, int *sout)
 {
-    int k_star = K, m_star = TB_M[K], s_star = 0;
-
+    int k, s = 0;
     if (nrm <= TB_THETA[K]) {
-        /* no scaling needed: the first row whose theta covers ||A|| */
-        int k = K;
-        for (int j = 1; j <= K; ++j) {
-            if (nrm <= TB_THETA[j]) { k = j; break; }
-        }
-        k_star = k;
-        m_star = TB_M[k];
-        s_star = 0;
-        if (option == 2) {
-            /* trade polynomial products for squarings when it is cheaper */
-            if (k >= 8 && nrm <= 2.0 * TB_THETA[k - 2]) {
-                k_star = k - 2; m_star = TB_M[k_star]; s_star = 1;
-            } else if (k == 9 && nrm <= 4.0 * TB_THETA[k - 3]) {
-                k_star = k - 3; m_star = TB_M[k_star]; s_star = 2;
-            }
-        }
+        k = 1;
+        while (nrm > TB_THETA[k]) ++k;
     } else {
-        /* s-hat = ceil(log2(nrm / theta_K)): the smallest s with
-         * nrm <= theta_K * 2^s.  Both sides are exact doubles, so the
-         * comparison is exact. */
-        int sh = 0;
-        while (nrm > ldexp(TB_THETA[K], sh)) ++sh;
-        s_star = sh;
-        double x = ldexp(nrm, -sh);            /* ||A|| / 2^s-hat, exact */
-        if (option > 0) {
-            if (K >= 7 && x <= TB_THETA[K - 1]) {
-                k_star = K - 1; m_star = TB_M[k_star];
-            } else if (option == 2) {
-                if (K >= 8 && x <= 2.0 * TB_THETA[K - 2]) {
-                    k_star = K - 2; m_star = TB_M[k_star]; s_star = sh + 1;
-                } else if (K == 9 && x <= 4.0 * TB_THETA[K - 3]) {
-                    k_star = K - 3; m_star = TB_M[k_star]; s_star = sh + 2;
-                }
-            }
+        k = K;
+        while (nrm > ldexp(TB_THETA[K], s)) ++s;
+    }
+    for (int t = 0; t < 3; ++t) {
+        const select_trade *tr = &SELECT_TRADES[t];
+        if (option < tr->min_option || k < tr->k_lo || k > tr->k_hi) continue;
+        if (ldexp(nrm, -(s + tr->ds)) <= TB_THETA[k + tr->dk]) {
+            k += tr->dk;
+            s += tr->ds;
+            break;
         }
     }
-    *kout = k_star;
-    *mout = m_star;
-    *sout = s_star;
+    *kout = k;
+    *mout = TB_M[k];
+    *sout = s;
 }
 
 /* ---- dense helpers (row-major n x n) -------------------------------------- */
