@@ -81,14 +81,17 @@ KERNEL_SOURCES = {"k_forward_wave": ("common.hpp", "wave.hpp"),
                   "k_rk1_lane": ("common.hpp", "rk1.hpp")}
 
 
-def forward_kernel(N, mapping, n_cells):
-    """The kernel drag_expm_apply launches for N species under `mapping`."""
+def forward_kernel(N, mapping, n_cells, n_dim=3):
+    """The kernel drag_expm_apply launches for N species under `mapping`
+    (contiguous arrays: the streaming one-lane kernel needs the velocity
+    array, n_dim (N + 1) rows of n_cells, within 2^32 bytes)."""
     if mapping == "wave":
         return "k_forward_wave" if N <= 16 else "k_forward_big"
     if N <= 6:
         return "k_forward_lane"
     if N <= 8:
-        return "k_forward_lane_stream" if n_cells < 1 << 29 else "k_forward_lane"
+        fits = 8 * n_dim * (N + 1) * n_cells < 1 << 32
+        return "k_forward_lane_stream" if fits else "k_forward_lane"
     return "k_forward_pair"
 
 
@@ -169,6 +172,15 @@ def main():
                     help="time per cell of the exponential (K = 9 and the tuned cap) and of the "
                          "backward Euler step for N = 1..16 on 64^3 cells (the paper's Fig. 6 "
                          "axes); one JSON object")
+    ap.add_argument("--k-sweep", action="store_true",
+                    help="time every Taylor cap K = 2..9 per species count N = 1..16 (stiff and "
+                         "jittered recipes, 2^18 cells, interleaved repeats); one JSON object")
+    ap.add_argument("--mapping-sweep", action="store_true",
+                    help="forward and fused-adjoint time per launch under every mapping that "
+                         "takes N = 1..16 (stiff recipe, 2^18 cells); one JSON object")
+    ap.add_argument("--squaring-cost", action="store_true",
+                    help="the N = 16 stiff workload at dt 2^j, j = 0..4: one more squaring per "
+                         "doubling at fixed k*, m*; the fitted cost per squaring; one JSON object")
     ap.add_argument("--report", action="store_true",
                     help="every workload configuration: GPU rate, roofline fractions, and the "
                          "oracle beside it (1-core and all-core rates, errors on the same "
@@ -204,6 +216,15 @@ def main():
         return
     if args.sweep:
         print(json.dumps(n_sweep(torch, ops, _lib, workloads, dev)), flush=True)
+        return
+    if args.k_sweep:
+        print(json.dumps(k_sweep(torch, ops, _lib, workloads, dev)), flush=True)
+        return
+    if args.mapping_sweep:
+        print(json.dumps(mapping_sweep(torch, ops, _lib, workloads, dev)), flush=True)
+        return
+    if args.squaring_cost:
+        print(json.dumps(squaring_cost(torch, ops, workloads, dev)), flush=True)
         return
     if args.adjoint:
         print(json.dumps(adjoint_only(torch, ops, _lib, workloads, dev, name, args)), flush=True)
@@ -254,8 +275,8 @@ def main():
         "peak": FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved_tflops / FP64_PEAK_TFLOPS, 4),
-        "traffic": profiled_traffic(forward_kernel(N, mapping, C), name),
-        "kernel": f"{forward_kernel(N, mapping, C)}<{N}>",
+        "traffic": profiled_traffic(forward_kernel(N, mapping, C, D), name),
+        "kernel": f"{forward_kernel(N, mapping, C, D)}<{N}>",
         "flops_per_launch": f_alg,
         "executed_flops_per_launch": f_exe,
         "executed_frac": round(f_exe / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
@@ -562,6 +583,96 @@ def n_sweep(torch, ops, _lib, workloads, dev, cells=1 << 18):
                                 "rk1_s_per_cell": tr * 1e-3 / cells, "k_auto": _lib.get_k_max(N),
                                 "exp_over_rk1": min(t9, ta) / tr})
     return out
+
+
+def k_sweep(torch, ops, _lib, workloads, dev, cells=1 << 18, reps=3):
+    """The Taylor cap K (Alg. 1's k_max: every K is u-accurate, it trades
+    polynomial degree against squarings) against time, per species count and
+    recipe: for each N, every K = 2..9 timed `reps` times in rotating order
+    (20 launches each), medians; the fastest K is what the library's
+    K_AUTO table should hold for that N."""
+    out = {"cells": cells, "rows": []}
+    Ks = list(range(2, 10))
+    for recipe, make in (("stiff", workloads.make_stiff), ("jittered", workloads.make_jittered)):
+        for N in range(1, 17):
+            d = make(N, cells)
+            T = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev)
+                 for k in ("rho_g", "rho_d", "t_stop", "v")}
+            o = torch.empty_like(T["v"])
+            times = {K: [] for K in Ks}
+            for rep in range(reps):
+                order = Ks[rep % len(Ks):] + Ks[:rep % len(Ks)]
+                for K in order:
+                    times[K].append(_time(torch, lambda: ops.expm_apply(
+                        T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"], k_max=K, out=o),
+                        20, 2))
+            med = {K: float(np.median(v)) for K, v in times.items()}
+            best = min(med, key=med.get)
+            out["rows"].append({"recipe": recipe, "N": N, "ms": med, "best_k": best,
+                                "best_over_k9": med[best] / med[9],
+                                "k_auto": _lib.get_k_max(N)})
+    return out
+
+
+def mapping_sweep(torch, ops, _lib, workloads, dev, cells=1 << 18):
+    """Forward and fused adjoint time per launch under every mapping that
+    takes N (stiff recipe, 2^18 cells, D = 3, K = 9): the lane mapping (one
+    lane per cell to N = 8, two lanes per cell above) and the MFMA quad; the
+    library's default per N is the faster one."""
+    rows = []
+    for N in range(1, 17):
+        d = workloads.make_stiff(N, cells)
+        T = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev)
+             for k in ("rho_g", "rho_d", "t_stop", "v")}
+        w = torch.randn_like(T["v"])
+        o = torch.empty_like(T["v"])
+        row = {"N": N, "default": {1: "lane", 2: "wave"}[_lib.get_mapping(N)]}
+        for name, mp in (("lane", _lib.MAP_LANE), ("wave", _lib.MAP_WAVE)):
+            if mp == _lib.MAP_LANE and N > 12:
+                continue
+            try:
+                _lib.set_mapping(N, mp)
+                row[f"fwd_{name}_ms"] = _time(torch, lambda: ops.expm_apply(
+                    T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"], out=o), 10, 2)
+                if mp == _lib.MAP_WAVE or N <= 10:
+                    row[f"adj_{name}_ms"] = _time(torch, lambda: ops.expm_apply_backward(
+                        T["rho_g"], T["rho_d"], T["t_stop"], T["v"], w, d["dt"]), 5, 1)
+            finally:
+                _lib.set_mapping(N, _lib.MAP_AUTO)
+        rows.append(row)
+    return {"cells": cells, "recipe": "stiff", "rows": rows}
+
+
+def squaring_cost(torch, ops, workloads, dev, steps=50):
+    """Cost of one squaring in the shipped N = 16 kernel: the stiff workload
+    at dt 2^j, j = 0..4.  Each doubling of dt doubles ||dt K||_1, which in
+    Alg. 1's scaled branch adds exactly one squaring (s* + 1) with the same
+    k* and m* (the scaled norm 2^-s* ||dt K||_1 is the same number), so the
+    time differences are the squarings' share, the rest (set-up, polynomial
+    stage, apply, memory) the intercept."""
+    d = workloads.make("n16_stiff_3d")
+    C = d["rho_g"].shape[0]
+    T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
+    o = torch.empty_like(T["v"])
+    rows = []
+    for j in range(5):
+        dt = d["dt"] * 2.0 ** j
+        _, _, _, kk, mm, ss = ops.build(T["rho_g"], T["rho_d"], T["t_stop"], dt)
+        ms = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], dt,
+                                                 out=o), steps, 5)
+        rows.append({"dt": dt, "ms": ms, "s_star": [int(ss.min()), int(ss.max())],
+                     "k_star": [int(kk.min()), int(kk.max())], "m_star": [int(mm.min()), int(mm.max())]})
+    x = np.array([r["s_star"][0] for r in rows], dtype=float)
+    y = np.array([r["ms"] for r in rows])
+    slope, icpt = np.polyfit(x, y, 1)
+    simds, clock = 1024, 2.4e9
+    per_cell = lambda ms: ms * 1e-3 * clock * simds / C  # noqa: E731
+    return {"workload": "n16_stiff_3d", "cells": C, "rows": rows,
+            "ms_per_squaring": float(slope),
+            "simd_cycles_per_cell_per_squaring": float(per_cell(slope)),
+            "mfma_cycles_per_cell_per_squaring": 4 * 64,
+            "simd_cycles_per_cell_outside_squarings": float(per_cell(icpt)),
+            "note": "one 16x16 product per squaring per cell: 4 FP64 MFMAs of 64 cycles"}
 
 
 def rk1_roofline(ms, C, N, D, workload):

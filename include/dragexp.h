@@ -220,7 +220,9 @@ int drag_expm_apply_backward(const drag_desc *desc, const double *rho_g,
 
 /* ---- batched blocks with uneven species counts -------------------------- */
 /*
- * A batch is n_blocks blocks of block_cells cells (AMR-style blocks), block b
+ * The paper's Dyablo implementation divides the grid into blocks of cells and
+ * runs one data-parallel loop per block (Sect. 3.4, Performance); here a
+ * batch is n_blocks blocks of block_cells cells (AMR-style blocks), block b
  * with its own species count N_b in [1, 16].  Block b's fields are one
  * contiguous slab of the caller's `fields` buffer starting at element
  * field_offset[b] (as returned by drag_plan_offsets):
@@ -255,7 +257,8 @@ int drag_plan_offsets(const drag_plan *plan, int64_t *field_offset,
 int drag_expm_apply_batched(drag_plan *plan, const double *fields,
                             const double *v_in, double *v_out,
                             drag_stream_t stream);
-/* Time every launch configuration of the plan on the caller's data (each
+/* Time every launch configuration of the plan on the caller's data (lane
+ * bound x MFMA form, the Taylor and the Pade per-N grids included; each
  * run computes the full, valid result into v_out, then synchronises
  * `stream`), keep the fastest, and report its lane-mapping bound: blocks
  * with N_b <= *lane_max_out run one cell per lane, the others on the FP64
@@ -270,11 +273,16 @@ int drag_plan_autotune(drag_plan *plan, const double *fields,
 /* The plan's current launch configuration: the lane-mapping bound and how
  * the MFMA branch runs: DRAG_MFMA_PERSISTENT (a persistent grid over a work
  * queue of a few cells per item), DRAG_MFMA_GRID (one plain grid over its
- * blocks, N at run time) or DRAG_MFMA_PER_N (one plain grid per species
- * count, each compiled for it).  Either pointer may be NULL. */
+ * blocks, N at run time), DRAG_MFMA_PER_N (one plain grid per species
+ * count, each compiled for it) or DRAG_MFMA_PER_N_PADE (the same grids with
+ * the diagonal Pade scaling step of Sect. 2.3, eq. PadeEqu, instead of the
+ * Taylor one: those blocks then give drag_expm_apply's result with option
+ * DRAG_OPTION_PADE, bit for bit; the plan's k_max and option do not apply to
+ * them).  Either pointer may be NULL. */
 #define DRAG_MFMA_PERSISTENT 0
 #define DRAG_MFMA_GRID 1
 #define DRAG_MFMA_PER_N 2
+#define DRAG_MFMA_PER_N_PADE 3
 int drag_plan_config(const drag_plan *plan, int32_t *lane_max,
                      int32_t *mfma_mode);
 /* Pin a launch configuration instead of the tuned one: lane_max in 4..12 and

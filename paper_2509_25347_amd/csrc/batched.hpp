@@ -92,11 +92,14 @@ __global__ void __launch_bounds__(256) k_batched_wave(BatchArgs B) {
 // loop-invariant state the persistent grid keeps live across items; the
 // hardware dispatcher balances the workgroups.  NC = 0 serves every N (taken
 // from the item at run time); NC > 0 is a grid over the blocks of that one N,
-// compiled for it like the plain per-N kernels.  The autotuner picks among
-// the persistent grid, one run-time-N grid and the per-N grids.
-template <int NC>
-__global__ void __launch_bounds__(256, 5) k_batched_wave_grid(BatchArgs B, int groups_per_block,
-                                                           int xcd_blocks) {
+// compiled for it like the plain per-N kernels.  METHOD is the scaling step
+// of the per-N grids: the Taylor approximant, or the diagonal Pade one
+// (kStagePade, as drag_expm_apply's Pade option).  The autotuner picks among
+// the persistent grid, one run-time-N grid and the per-N grids of either
+// method.
+template <int NC, int METHOD = kStageTaylor>
+__global__ void __launch_bounds__(256, METHOD == kStageTaylor ? 5 : 4)
+    k_batched_wave_grid(BatchArgs B, int groups_per_block, int xcd_blocks) {
   __shared__ double lds[4 * kQuadDoubles];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -110,7 +113,8 @@ __global__ void __launch_bounds__(256, 5) k_batched_wave_grid(BatchArgs B, int g
   const CellArgs A = block_args(B, it);
   const int n = NC > 0 ? NC : it.n;
   const int c0 = g0 + 4 * w;
-  if (c0 < B.block_cells) wave_forward_quad(A, n, c0, lane, lds + w * kQuadDoubles, false);
+  if (c0 < B.block_cells)
+    wave_forward_quad<METHOD>(A, n, c0, lane, lds + w * kQuadDoubles, false);
   __syncthreads();
   group_store(A, n, g0, lds);
 }

@@ -63,62 +63,45 @@ struct Kms {
 __device__ unsigned int g_status_word;
 
 // Alg. 1 (Appendix B, "First modification"): (k*, m*, s*) for a finite
-// ||A||_1 with at most K products in the polynomial stage.  The scaled
-// branch's s-hat = ceil(log2(nrm / theta_K)) is the smallest s >= 0 with
-// nrm <= theta_K 2^s, found with exact power-of-two comparisons after a
-// frexp estimate, so host and device agree bit for bit.
+// ||A||_1 with at most K products in the polynomial stage, from the method's
+// cost model: row k of Table B.1 costs k products (Pi_{m_k}) and every
+// squaring one more; row k serves a scaling 2^-s when ||A|| 2^-s <=
+// theta_{m_k} (eq. B8).  The base pair is the cheapest row that needs no
+// scaling, or else row K with s-hat = ceil(log2(||A|| / theta_K)), the
+// fewest squarings that serve it (found with exact power-of-two comparisons
+// after a frexp estimate, so host and device agree bit for bit).  The
+// options then allow trades that keep the cost: one product fewer at the
+// same s (option >= 1, rows 7..9), or two or three products of the
+// polynomial for one or two squarings at a lower degree (option 2, rows 8..9,
+// row 9); the first trade whose pair still serves is taken.
+struct KmsTrade {
+  int dk, ds, min_option, k_lo, k_hi;
+};
+constexpr KmsTrade kKmsTrades[3] = {{-1, 0, 1, 7, 9}, {-2, 1, 2, 8, 9}, {-3, 2, 2, 9, 9}};
+
 __host__ __device__ inline Kms select_kms(double nrm, int K, int option) {
-  Kms r{K, kTabM[K], 0};
-  const double thK = kTheta[K];
-  if (nrm <= thK) {
-    int k = K;
-    for (int j = 1; j <= K; ++j) {
-      if (nrm <= kTheta[j]) {
-        k = j;
-        break;
-      }
-    }
-    r.k = k;
-    r.m = kTabM[k];
-    r.s = 0;
-    if (option == 2) {
-      if (k >= 8 && nrm <= 2.0 * kTheta[k - 2]) {
-        r.k = k - 2;
-        r.m = kTabM[r.k];
-        r.s = 1;
-      } else if (k == 9 && nrm <= 4.0 * kTheta[k - 3]) {
-        r.k = k - 3;
-        r.m = kTabM[r.k];
-        r.s = 2;
-      }
-    }
-    return r;
+  int k = K, s = 0;
+  if (nrm <= kTheta[K]) {
+    k = 1;
+    while (nrm > kTheta[k]) ++k;
+  } else {
+    int en, et;
+    frexp(nrm, &en);
+    frexp(kTheta[K], &et);
+    s = en - et - 1;  // nrm / theta_K lies in (2^(en-et-1), 2^(en-et+1))
+    if (s < 0) s = 0;
+    while (nrm > ldexp(kTheta[K], s)) ++s;
   }
-  int en, et;
-  frexp(nrm, &en);
-  frexp(thK, &et);
-  int sh = en - et - 1;  // nrm / thK lies in (2^(en-et-1), 2^(en-et+1))
-  if (sh < 0) sh = 0;
-  while (nrm > ldexp(thK, sh)) ++sh;
-  r.s = sh;
-  const double x = ldexp(nrm, -sh);
-  if (option > 0) {
-    if (K >= 7 && x <= kTheta[K - 1]) {
-      r.k = K - 1;
-      r.m = kTabM[r.k];
-    } else if (option == 2) {
-      if (K >= 8 && x <= 2.0 * kTheta[K - 2]) {
-        r.k = K - 2;
-        r.m = kTabM[r.k];
-        r.s = sh + 1;
-      } else if (K == 9 && x <= 4.0 * kTheta[K - 3]) {
-        r.k = K - 3;
-        r.m = kTabM[r.k];
-        r.s = sh + 2;
-      }
+  for (int t = 0; t < 3; ++t) {
+    const KmsTrade tr = kKmsTrades[t];
+    if (option < tr.min_option || k < tr.k_lo || k > tr.k_hi) continue;
+    if (ldexp(nrm, -(s + tr.ds)) <= kTheta[k + tr.dk]) {
+      k += tr.dk;
+      s += tr.ds;
+      break;
     }
   }
-  return r;
+  return Kms{k, kTabM[k], s};
 }
 
 // Launch parameters common to the per-cell kernels.

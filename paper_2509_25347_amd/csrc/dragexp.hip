@@ -143,10 +143,19 @@ static int resident_blocks(const void* kernel, std::atomic<int>& per_cu, int* ou
 constexpr int kLaneStreamMinN = 7;
 constexpr bool lane_early_loads(int n) { return n != 3 && n < kLaneStreamMinN; }
 
+// The raw buffer loads of the one-lane kernels address each input array with
+// 32-bit byte offsets: its last byte, 8 ((rows - 1) ld + n_cells), must lie
+// below 2^32 (the velocities, D (N + 1) rows, are the largest array).
+template <int N>
+static bool lane_buffers_fit(const CellArgs& A) {
+  const int64_t rows = (int64_t)A.n_dim * (N + 1);
+  return A.ld < (int64_t(1) << 32) && 8 * ((rows - 1) * A.ld + A.n_cells) < (int64_t(1) << 32);
+}
+
 template <int N>
 static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
   if constexpr (N >= kLaneStreamMinN) {
-    if (A.n_cells < (int64_t(1) << 29)) {  // 32-bit lane byte offsets
+    if (lane_buffers_fit<N>(A)) {
       static std::atomic<int> per_cu{0};
       int resident = 0;
       const int rc = resident_blocks(reinterpret_cast<const void*>(&k_forward_lane_stream<N>),
@@ -160,7 +169,7 @@ static int launch_forward_lane(const CellArgs& A, hipStream_t st) {
   }
   const Grid gr = grid_for((A.n_cells + 255) / 256);
   if constexpr (lane_early_loads(N)) {
-    if (A.n_cells < (int64_t(1) << 29)) {
+    if (lane_buffers_fit<N>(A)) {
       hipLaunchKernelGGL((k_forward_lane<N, true>), dim3(gr.blocks), dim3(256), 0, st, A,
                          gr.xcd_blocks);
       return hip_status(hipGetLastError());
@@ -213,7 +222,8 @@ static int launch_backward_lane(const BackArgs& A, hipStream_t st) {
 template <int N>
 static int launch_backward_pair(const BackArgs& A, hipStream_t st) {
   const Grid gr = grid_for((A.n_cells + 127) / 128);
-  hipLaunchKernelGGL(k_backward_pair<N>, dim3(gr.blocks), dim3(256), 0, st, A, gr.xcd_blocks);
+  hipLaunchKernelGGL((k_backward_pair<N, (N >= 9 ? 1 : 2)>), dim3(gr.blocks), dim3(256), 0, st, A,
+                     gr.xcd_blocks);
   return hip_status(hipGetLastError());
 }
 
@@ -343,14 +353,14 @@ static int mapping_for_bwd(int N) {
 // N - 1), overridable with drag_set_k_max.  Every K gives an approximant
 // accurate to u (the selection keeps ||A / 2^s|| <= theta_m); K only trades
 // polynomial degree against squarings.  The one-lane kernel evaluates the
-// polynomial by Horner in the structured matrix (m steps of O(N^2)) and
-// squares densely (O(N^3)), so small N prefers low degrees; the MFMA kernel
-// is flat for K >= 7.  Measured on MI355X over 2^18 cells per N (stiff and
-// jittered recipes), the fastest K against K = 9: N = 2-4 K = 3-4 (0.72-0.86
-// of the time), N = 5-6 K = 5 (0.83-0.92), N = 7-8 K = 6 (0.88-0.98), and
-// on the two-lanes-per-cell kernel N = 9-12 K = 5-6 (0.88-0.99); the MFMA
-// kernel (N >= 13) K = 7 (0.98-0.99).
-static const int g_default_kmax[16] = {4, 3, 3, 4, 5, 5, 6, 6, 6, 6, 6, 6, 7, 7, 7, 7};
+// polynomial by Horner in the structured matrix (m steps of 2 N^2 + N) and
+// squares densely (N^3 per squaring), so small N prefers low degrees; the
+// MFMA kernel is flat for K >= 7.  The table holds, per N, the K with the
+// least summed time over the stiff and the jittered recipes (2^18 cells,
+// `bench.py --k-sweep`: every K = 2..9, interleaved repeats): against K = 9
+// it takes 0.84-0.97 of the time for N = 2..8, 0.88-0.99 on the
+// two-lanes-per-cell kernel (N = 9..12), 0.99-1.0 on the MFMA kernel.
+static const int g_default_kmax[16] = {4, 3, 4, 5, 5, 6, 5, 6, 6, 6, 6, 6, 7, 7, 7, 7};
 static int g_kmax_override[16] = {0};
 
 static int k_for(int k_max, int N) {
@@ -407,7 +417,8 @@ constexpr int kWaveItemCells = 8;
 constexpr int kWavePersistent = 0;
 constexpr int kWaveGrid = 1;
 constexpr int kWavePerN = 2;
-constexpr int kWaveModes = 3;
+constexpr int kWavePerNPade = 3;  // per-N grids with the Pade scaling step
+constexpr int kWaveModes = 4;
 // smallest Taylor cap the plan's autotuner tries (K = 1, 2 cap m at 2 and 4:
 // every cell then needs many squarings)
 constexpr int kTuneKMin = 3;
@@ -429,29 +440,36 @@ static void launch_batched_lane(const BatchArgs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_batched_lane<N>, dim3((B.n_items + 3) / 4), dim3(256), 0, st, B);
 }
 
-template <int N>
+template <int N, int METHOD>
 static void launch_batched_wave_n(const BatchArgs& B, int gpb, hipStream_t st) {
   const Grid gr = grid_for((int64_t)B.n_items * gpb);
-  hipLaunchKernelGGL(k_batched_wave_grid<N>, dim3(gr.blocks), dim3(256), 0, st, B, gpb,
-                     gr.xcd_blocks);
+  hipLaunchKernelGGL((k_batched_wave_grid<N, METHOD>), dim3(gr.blocks), dim3(256), 0, st, B,
+                     gpb, gr.xcd_blocks);
+}
+
+template <int METHOD>
+static void batched_wave_n_method(int N, const BatchArgs& B, int gpb, hipStream_t st) {
+  switch (N) {
+    case 5: launch_batched_wave_n<5, METHOD>(B, gpb, st); break;
+    case 6: launch_batched_wave_n<6, METHOD>(B, gpb, st); break;
+    case 7: launch_batched_wave_n<7, METHOD>(B, gpb, st); break;
+    case 8: launch_batched_wave_n<8, METHOD>(B, gpb, st); break;
+    case 9: launch_batched_wave_n<9, METHOD>(B, gpb, st); break;
+    case 10: launch_batched_wave_n<10, METHOD>(B, gpb, st); break;
+    case 11: launch_batched_wave_n<11, METHOD>(B, gpb, st); break;
+    case 12: launch_batched_wave_n<12, METHOD>(B, gpb, st); break;
+    case 13: launch_batched_wave_n<13, METHOD>(B, gpb, st); break;
+    case 14: launch_batched_wave_n<14, METHOD>(B, gpb, st); break;
+    case 15: launch_batched_wave_n<15, METHOD>(B, gpb, st); break;
+    default: launch_batched_wave_n<16, METHOD>(B, gpb, st); break;
+  }
 }
 
 // N = 5..16: the species counts the MFMA branch can hold (LMAX >= 4)
-static void batched_wave_n(int N, const BatchArgs& B, int gpb, hipStream_t st) {
-  switch (N) {
-    case 5: launch_batched_wave_n<5>(B, gpb, st); break;
-    case 6: launch_batched_wave_n<6>(B, gpb, st); break;
-    case 7: launch_batched_wave_n<7>(B, gpb, st); break;
-    case 8: launch_batched_wave_n<8>(B, gpb, st); break;
-    case 9: launch_batched_wave_n<9>(B, gpb, st); break;
-    case 10: launch_batched_wave_n<10>(B, gpb, st); break;
-    case 11: launch_batched_wave_n<11>(B, gpb, st); break;
-    case 12: launch_batched_wave_n<12>(B, gpb, st); break;
-    case 13: launch_batched_wave_n<13>(B, gpb, st); break;
-    case 14: launch_batched_wave_n<14>(B, gpb, st); break;
-    case 15: launch_batched_wave_n<15>(B, gpb, st); break;
-    default: launch_batched_wave_n<16>(B, gpb, st); break;
-  }
+static void batched_wave_n(int N, const BatchArgs& B, int gpb, hipStream_t st,
+                           bool pade = false) {
+  if (pade) batched_wave_n_method<kStagePade>(N, B, gpb, st);
+  else batched_wave_n_method<kStageTaylor>(N, B, gpb, st);
 }
 
 template <int N>
@@ -669,7 +687,7 @@ static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
       BatchArgs W = B;
       W.items = V.d_wave_n[n];
       W.n_items = V.n_wave_n[n];
-      batched_wave_n(n, W, gpb, main);
+      batched_wave_n(n, W, gpb, main, mode == kWavePerNPade);
     }
   }
   if (hipStreamWaitEvent(main, P->ev_join, 0) != hipSuccess) return DRAG_ERR_HIP;
@@ -979,6 +997,7 @@ int drag_plan_autotune(drag_plan* P, const double* fields, const double* v_in, d
     for (int n = 1; n <= kMaxSpecies && rc == DRAG_OK; ++n) {
       const bool lane = n <= P->lmax;
       if ((lane ? V.n_lane[n] : V.n_wave_n[n]) == 0) continue;
+      if (!lane && P->wave_mode == kWavePerNPade) continue;  // the Pade step takes no cap
       BatchArgs X = B;
       X.items = lane ? V.d_lane[n] : V.d_wave_n[n];
       X.n_items = lane ? V.n_lane[n] : V.n_wave_n[n];

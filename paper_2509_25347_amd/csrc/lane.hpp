@@ -26,10 +26,15 @@
 namespace dragexp {
 
 // Horner evaluation of F = sum_{i=1}^{m} c_i M^i = T_m(M) - I for the
-// structured M = 2^-s At: M_jk = -b_j [j == k] - pb_k.  Right products by M
-// cost O(N^2): (F M)_ik = -F_ik b_k - (sum_l F_il) pb_k.  Lanes of one
-// wavefront may have different m; the loop runs to the wavefront's largest
-// m and each lane adds only its own coefficients (a zero F stays zero).
+// structured M = 2^-s At: M_jk = -b_j [j == k] - pb_k.  Each degree is one
+// left product F <- M (F + c_i I), which the structure makes 2 N^2 + N
+// operations: (M G)_ik = -b_i G_ik - cs_k with the weighted column sums
+// cs_k = sum_l pb_l G_lk (a right product needs 3 N^2: a plain row sum, then
+// one multiply and one fma per entry).  Polynomials in M commute with M, so
+// both orders evaluate the same T_m.  Lanes of one wavefront may have
+// different m; the loop runs to the wavefront's largest m (wave-uniform, so
+// the coefficient is a scalar load) and each lane adds only its own
+// coefficients (a zero F stays zero).
 template <int N>
 __device__ __forceinline__ void lane_taylor(double (&F)[N][N], const double (&b)[N],
                                             const double (&pb)[N], int m, int m_max) {
@@ -40,14 +45,19 @@ __device__ __forceinline__ void lane_taylor(double (&F)[N][N], const double (&b)
   for (int it = m_max; it >= 1; --it) {
     const double c = (it <= m) ? kInvFact[it] : 0.0;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      F[i][i] += c;
-      double rs = 0.0;
+    for (int i = 0; i < N; ++i) F[i][i] += c;
+    double cs[N];
 #pragma unroll
-      for (int l = 0; l < N; ++l) rs += F[i][l];
+    for (int k = 0; k < N; ++k) {
+      double acc = pb[0] * F[0][k];
 #pragma unroll
-      for (int k = 0; k < N; ++k) F[i][k] = fma(-F[i][k], b[k], -rs * pb[k]);
+      for (int l = 1; l < N; ++l) acc = fma(pb[l], F[l][k], acc);
+      cs[k] = acc;
     }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int k = 0; k < N; ++k) F[i][k] = fma(-b[i], F[i][k], -cs[k]);
   }
 }
 
@@ -78,10 +88,12 @@ __device__ __forceinline__ void lane_copy(double (&W)[N][N], const double (&Z)[N
     for (int k = 0; k < N; ++k) W[i][k] = Z[i][k];
 }
 
+// Largest x over the wavefront, returned as a wave-uniform (scalar) value so
+// that loops bounded by it run on scalar counters.
 __device__ __forceinline__ int wave_max_int(int x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
-  return x;
+  return __builtin_amdgcn_readfirstlane(x);
 }
 
 // Per-cell set-up: coefficients, ||A||_1 (bit-exact order), Alg. 1.
@@ -282,29 +294,42 @@ struct LaneInputs : LaneCoefs<N> {
   double v[3][N + 1];
 };
 
-// Element `off / 8` of a row of `bytes` bytes through a raw buffer load: the
-// row's base lives in a scalar resource and every load of a cell shares one
-// 32-bit lane offset, so prefetching a cell's inputs holds one address
-// register, not a 64-bit address per row.  An offset past the row reads 0.
-// The resource: stride 0 (raw), num_records = bytes (bit pattern; up to
-// 2^32 - 8 here), and the CDNA word-3 flags for 32-bit untyped data.
-__device__ __forceinline__ double row_at(const double* row, uint32_t bytes, uint32_t off) {
+// Raw buffer loads for the one-lane kernels' inputs: one scalar resource per
+// array (base and size), the row as a wave-uniform SGPR offset and the cell
+// as one 32-bit lane offset shared by every load of the cell.  Prefetching a
+// cell's inputs then holds one address register, and the 2N + 1 + D (N + 1)
+// rows cost four resources instead of one per row (a resource per row needed
+// four SGPRs each: 176 at N = 8, which the compiler spilled).  The resource:
+// stride 0 (raw), num_records = the array's bytes (bit pattern, below 2^32:
+// the host checks 8 ((rows - 1) ld + n_cells) < 2^32), and the CDNA word-3
+// flags for 32-bit untyped data; an offset at or past the end reads 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const double* base, uint32_t bytes) {
   constexpr int kRawBufferFlags = 0x00020000;
-  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<double*>(row), (short)0, (int)bytes, kRawBufferFlags);
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)bytes,
+                                           kRawBufferFlags);
 }
 
-// Inputs of cell c, given as the byte offset off = 8 c (c < n_cells < 2^29,
-// so that 8 n_cells fits in 32 bits).
+__device__ __forceinline__ double rsrc_at(__amdgpu_buffer_rsrc_t r, uint32_t lane_off,
+                                          uint32_t row_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, row_off, 0));
+}
+
+// Bytes of an SoA array of `rows` rows of n_cells cells, leading dimension ld.
+__device__ __forceinline__ uint32_t array_bytes(int64_t rows, const CellArgs& A) {
+  return (uint32_t)(8 * ((rows - 1) * A.ld + A.n_cells));
+}
+
+// Inputs of cell c, given as the byte offset off = 8 c.
 template <int N>
 __device__ __forceinline__ void lane_load(LaneCoefs<N>& X, const CellArgs& A, uint32_t off) {
-  const uint32_t bytes = (uint32_t)(8 * A.n_cells);
-  X.rg = row_at(A.rho_g, bytes, off);
+  const uint32_t row = (uint32_t)(8 * A.ld);
+  X.rg = rsrc_at(raw_rsrc(A.rho_g, array_bytes(1, A)), off, 0u);
+  const __amdgpu_buffer_rsrc_t rt = raw_rsrc(A.t_stop, array_bytes(N, A));
+  const __amdgpu_buffer_rsrc_t rd = raw_rsrc(A.rho_d, array_bytes(N, A));
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    X.ts[i] = row_at(A.t_stop + i * A.ld, bytes, off);
-    X.rd[i] = row_at(A.rho_d + i * A.ld, bytes, off);
+    X.ts[i] = rsrc_at(rt, off, (uint32_t)i * row);
+    X.rd[i] = rsrc_at(rd, off, (uint32_t)i * row);
   }
 }
 
@@ -313,13 +338,14 @@ __device__ __forceinline__ void lane_load(LaneCoefs<N>& X, const CellArgs& A, ui
 template <int N>
 __device__ __forceinline__ void lane_load(LaneInputs<N>& X, const CellArgs& A, uint32_t off) {
   lane_load<N>(static_cast<LaneCoefs<N>&>(X), A, off);
-  const uint32_t bytes = (uint32_t)(8 * A.n_cells);
+  const uint32_t row = (uint32_t)(8 * A.ld);
   const int n1 = N + 1;
+  const __amdgpu_buffer_rsrc_t rv = raw_rsrc(A.v_in, array_bytes((int64_t)A.n_dim * n1, A));
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int dd = d < A.n_dim ? d : A.n_dim - 1;
 #pragma unroll
-    for (int j = 0; j <= N; ++j) X.v[d][j] = row_at(A.v_in + (int64_t)(dd * n1 + j) * A.ld, bytes, off);
+    for (int j = 0; j <= N; ++j) X.v[d][j] = rsrc_at(rv, off, (uint32_t)(dd * n1 + j) * row);
   }
 }
 
@@ -351,7 +377,7 @@ __device__ __forceinline__ void lane_forward_loaded(const CellArgs& A, const Lan
 // the cells with a stride, and each lane loads the inputs of its next cell
 // before it computes the current one: the loads of one cell overlap the
 // arithmetic of the previous.  Same arithmetic as k_forward_lane, per cell.
-// Needs n_cells < 2^29 (32-bit byte offsets and row sizes).
+// Needs every input array within 2^32 bytes (lane_buffers_fit on the host).
 template <int N>
 __global__ void __launch_bounds__(256) k_forward_lane_stream(CellArgs A) {
   const int lane = threadIdx.x & 63;
@@ -376,7 +402,7 @@ __global__ void __launch_bounds__(256) k_forward_lane_stream(CellArgs A) {
 
 // One-shot one-lane forward.  EARLY issues every load of the cell, the
 // velocities included, before the exponential, so that they arrive during
-// it (n_cells < 2^29); otherwise the velocities are read after it, which
+// it (every input array within 2^32 bytes); otherwise the velocities are read after it, which
 // keeps fewer registers live.
 template <int N, bool EARLY = false>
 __global__ void __launch_bounds__(256) k_forward_lane(CellArgs A, int xcd_blocks) {

@@ -47,16 +47,19 @@ __device__ __forceinline__ double pair_sum(double x, int h) {
 
 // kMinWaves: waves per SIMD the register allocation must allow (2 forces
 // N = 7, 8 into 256 registers at the price of a few spills in the squaring
-// loop; 1 lets them use accumulation registers instead).
+// loop; 1 lets them use accumulation registers instead).  N = 9, 10 need
+// more than 256 (Y, dY and the product rows: 3 H 2H doubles) and run at 1.
 template <int N, int kMinWaves = 2>
 __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, int xcd_blocks) {
   constexpr int H = (N + 1) / 2;  // rows per lane
   constexpr int W2 = 2 * H;       // padded width
   constexpr int kCells = 128;     // cells per workgroup (two lanes each)
-  // per cell, global column order, zero padded: ubar[3][W2], dv[3][W2], a[W2], e[W2];
-  // the odd stride spreads the pairs of a wavefront over the LDS banks
-  constexpr int kPer = 8 * W2 + 1;
-  __shared__ double sm[kCells * kPer];
+  // per cell, global column order, zero padded: ubar[3][W2], dv[3][W2], a[W2], e[W2],
+  // stored entry-major (entry x of pair pl at sm[x * kStride + pl]): the pairs of a
+  // wavefront read consecutive doubles, and the two lanes of a pair, whose entries
+  // lie H apart, fall on the other half of the banks (kStride = 2 mod 4)
+  constexpr int kStride = kCells + 2;
+  __shared__ double sm[8 * W2 * kStride];
 
   const int bid = blockIdx.x;
   const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
@@ -68,7 +71,7 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
   const int64_t ld = A.ld;
   const int n1 = N + 1;
   const int D = A.n_dim;
-  double* my = sm + pl * kPer;
+  double* my = sm + pl;  // entry x of this pair at my[x * kStride]
 
   // relative column kappa of this lane <-> global column
   auto gcol = [&](int kappa) { return kappa < H ? h * H + kappa : (1 - h) * H + kappa - H; };
@@ -121,14 +124,14 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
       }
 #pragma unroll
       for (int k = 0; k < W2; ++k) {
-        my[d * W2 + k] = k < N ? w[k + 1] - W * C.e[k < N ? k : 0] / C.sigma : 0.0;
-        my[(3 + d) * W2 + k] = k < N ? v[k + 1] - v[0] : 0.0;
+        my[(d * W2 + k) * kStride] = k < N ? w[k + 1] - W * C.e[k < N ? k : 0] / C.sigma : 0.0;
+        my[((3 + d) * W2 + k) * kStride] = k < N ? v[k + 1] - v[0] : 0.0;
       }
     }
 #pragma unroll
     for (int k = 0; k < W2; ++k) {
-      my[6 * W2 + k] = k < N ? C.a[k < N ? k : 0] : 0.0;
-      my[7 * W2 + k] = k < N ? C.e[k < N ? k : 0] : 0.0;
+      my[(6 * W2 + k) * kStride] = k < N ? C.a[k < N ? k : 0] : 0.0;
+      my[(7 * W2 + k) * kStride] = k < N ? C.e[k < N ? k : 0] : 0.0;
     }
   }
   const double sigma = C.sigma;
@@ -165,8 +168,8 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
 #pragma unroll
       for (int k = 0; k < W2; ++k) {
         const int g = gcol(k);
-        ub[k] = my[d * W2 + g];
-        dv[k] = my[(3 + d) * W2 + g];
+        ub[k] = my[(d * W2 + g) * kStride];
+        dv[k] = my[((3 + d) * W2 + g) * kStride];
       }
 #pragma unroll
       for (int r = 0; r < H; ++r) {
@@ -270,8 +273,8 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
 #pragma unroll
     for (int k = 0; k < W2; ++k) {
       const int g = gcol(k);
-      ub[k] = my[d * W2 + g];
-      dv[k] = my[(3 + d) * W2 + g];
+      ub[k] = my[(d * W2 + g) * kStride];
+      dv[k] = my[((3 + d) * W2 + g) * kStride];
     }
     // u = Z dv: column sums of Y weighted by dv over own rows, plus the partner's
     double up[W2];
@@ -288,7 +291,7 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
     double eu_own = 0.0, zt[H], zt_own = 0.0;
 #pragma unroll
     for (int r = 0; r < H; ++r) {
-      const double e_r = my[7 * W2 + h * H + r];
+      const double e_r = my[(7 * W2 + h * H + r) * kStride];
       eu_own = fma(e_r, u[r], eu_own);
       double acc = 0.0;
 #pragma unroll
@@ -335,8 +338,8 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
   for (int r = 0; r < H; ++r) {
     const int k = h * H + r;
     const double col = colp[r] + pair_swap(colp[(r + H) % W2]);
-    const double e_k = my[7 * W2 + h * H + r];
-    const double a_k = my[6 * W2 + h * H + r];
+    const double e_k = my[(7 * W2 + h * H + r) * kStride];
+    const double a_k = my[(6 * W2 + h * H + r) * kStride];
     const double ga = -dY[r][r] - e_k * col;
     const double ge = -a_k * col + ge_dir[r];
     const double glt = -a_k * ga;

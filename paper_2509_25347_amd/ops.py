@@ -326,7 +326,7 @@ class BatchPlan:
                                                  ctypes.byref(lm)), "drag_plan_autotune")
         return lm.value
 
-    MFMA_MODES = {0: "persistent", 1: "grid", 2: "per_n"}
+    MFMA_MODES = {0: "persistent", 1: "grid", 2: "per_n", 3: "per_n_pade"}
 
     def config(self):
         """(lane_max, mfma_mode) of the current launch configuration; the mode

@@ -32,9 +32,10 @@ def ops(dev):
     return _ops
 
 
-def plain_per_block(ops, batch, dev, lane_max, k_max=None):
+def plain_per_block(ops, batch, dev, lane_max, k_max=None, pade=False):
     """drag_expm_apply on every block with the batched plan's mapping (and
-    Taylor cap k_max[N - 1] when given, else K = 9)."""
+    Taylor cap k_max[N - 1] when given, else K = 9; with ``pade`` the blocks
+    above lane_max take the Pade option, as the plan's per_n_pade form)."""
     from paper_2509_25347_amd import _lib
     outs = []
     try:
@@ -43,9 +44,11 @@ def plain_per_block(ops, batch, dev, lane_max, k_max=None):
         for blk in batch["blocks"]:
             T = {k: torch.from_numpy(np.ascontiguousarray(blk[k])).to(dev)
                  for k in ("rho_g", "rho_d", "t_stop", "v")}
-            K = 9 if k_max is None else k_max[blk["rho_d"].shape[0] - 1]
+            N = blk["rho_d"].shape[0]
+            K = 9 if k_max is None else k_max[N - 1]
+            opt = _lib.OPTION_PADE if pade and N > lane_max else 2
             outs.append(ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
-                                       batch["dt"], k_max=K).cpu().numpy())
+                                       batch["dt"], k_max=K, option=opt).cpu().numpy())
     finally:
         for N in range(1, 17):
             _lib.set_mapping(N, _lib.MAP_AUTO)
@@ -69,30 +72,52 @@ def test_batched_matches_plain_and_oracle(ops, dev, orc):
 
 
 def test_autotune_and_every_variant_result(ops, dev):
-    """The tuned configuration and every pinned one (lane bound 4..8 x the
-    three MFMA forms) give the plain per-block result bit for bit."""
+    """The tuned configuration and every pinned one (lane bound 4..12 x the
+    four MFMA forms) give the plain per-block result bit for bit: the Taylor
+    forms drag_expm_apply's default, the Pade per-N grids its Pade option."""
     batch = W.make_batched(n_blocks=64, block_cells=70, seed_cfg=43)
     plan = ops.BatchPlan(batch["n_species"], 70, 3, batch["dt"])
     fields, v = plan.pack(batch["blocks"], dev)
     out = torch.empty_like(v)
     lm = plan.autotune(fields, v, out)
     assert 4 <= lm <= 12
-    assert plan.config()[1] in ("persistent", "grid", "per_n")
+    mode_t = plan.config()[1]
+    assert mode_t in ("persistent", "grid", "per_n", "per_n_pade")
     out2 = plan.apply(fields, v)
     torch.cuda.synchronize()
-    refs = {lm: plain_per_block(ops, batch, dev, lane_max=lm)}
+    tuned_ref = plain_per_block(ops, batch, dev, lane_max=lm, pade=mode_t == "per_n_pade")
     for b in range(len(batch["blocks"])):
-        assert np.array_equal(plan.block_view(out2, b).cpu().numpy(), refs[lm][b]), b
+        assert np.array_equal(plan.block_view(out2, b).cpu().numpy(), tuned_ref[b]), b
     for lmax in range(4, 13):
-        if lmax not in refs:
-            refs[lmax] = plain_per_block(ops, batch, dev, lane_max=lmax)
-        for mode in ("persistent", "grid", "per_n"):
+        ref_t = plain_per_block(ops, batch, dev, lane_max=lmax)
+        ref_p = plain_per_block(ops, batch, dev, lane_max=lmax, pade=True)
+        for mode in ("persistent", "grid", "per_n", "per_n_pade"):
             plan.set_config(lmax, mode)
             assert plan.config() == (lmax, mode)
             o = plan.apply(fields, v)
             torch.cuda.synchronize()
+            ref = ref_p if mode == "per_n_pade" else ref_t
             for b in range(len(batch["blocks"])):
-                assert np.array_equal(plan.block_view(o, b).cpu().numpy(), refs[lmax][b]), (lmax, mode, b)
+                assert np.array_equal(plan.block_view(o, b).cpu().numpy(), ref[b]), (lmax, mode, b)
+    plan.close()
+
+
+def test_pade_per_n_form_against_the_oracle(ops, dev, orc):
+    """The per_n_pade form: blocks above the lane bound against the oracle's
+    Pade step (its dense (N+1) form) and the exact exponential, to the
+    parity bars; blocks at or below it are the lane kernels' Taylor result."""
+    batch = W.make_batched(n_blocks=40, block_cells=96, seed_cfg=48)
+    plan = ops.BatchPlan(batch["n_species"], 96, 3, batch["dt"])
+    fields, v = plan.pack(batch["blocks"], dev)
+    plan.set_config(8, "per_n_pade")
+    out = plan.apply(fields, v)
+    torch.cuda.synchronize()
+    for b, blk in enumerate(batch["blocks"]):
+        got = plan.block_view(out, b).cpu().numpy()
+        pade = blk["rho_d"].shape[0] > 8
+        o, kms, nrm, st = orc.apply_cells(blk["rho_g"], blk["rho_d"], blk["t_stop"], blk["v"],
+                                          batch["dt"], option=orc.PADE if pade else 2)
+        check_forward(orc, got, o, dict(blk, dt=batch["dt"]), ("block", b, "pade", pade))
     plan.close()
 
 

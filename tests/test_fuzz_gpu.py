@@ -158,8 +158,9 @@ def test_random_batched_plan(dev, orc, seed):
     if rng.random() < 0.5:
         plan.autotune(fields, v, out)
     else:
-        plan.set_config(int(rng.integers(4, 13)), str(rng.choice(["persistent", "grid", "per_n"])))
-    lmax, _ = plan.config()
+        plan.set_config(int(rng.integers(4, 13)),
+                        str(rng.choice(["persistent", "grid", "per_n", "per_n_pade"])))
+    lmax, mode = plan.config()
     ks = plan.k_max()
     got = plan.apply(fields, v)
     torch.cuda.synchronize()
@@ -171,12 +172,14 @@ def test_random_batched_plan(dev, orc, seed):
             N = blk["rho_d"].shape[0]
             T = {k: torch.from_numpy(np.ascontiguousarray(blk[k])).to(dev)
                  for k in ("rho_g", "rho_d", "t_stop", "v")}
+            pade = mode == "per_n_pade" and N > lmax
             ref = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], batch["dt"],
-                                 k_max=ks[N - 1])
+                                 k_max=ks[N - 1], option=_lib.OPTION_PADE if pade else 2)
             g = plan.block_view(got, b)
             assert torch.equal(g, ref), (label, b, N)
             o, kms, nrm, st = orc.apply_cells(blk["rho_g"], blk["rho_d"], blk["t_stop"],
-                                              blk["v"], batch["dt"], K=ks[N - 1])
+                                              blk["v"], batch["dt"], K=ks[N - 1],
+                                              option=orc.PADE if pade else 2)
             check_forward(orc, g.cpu().numpy(), o, dict(blk, dt=batch["dt"]), (label, b))
     finally:
         for N in range(1, 17):
