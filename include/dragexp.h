@@ -69,6 +69,8 @@ extern "C" {
 #define DRAG_ERR_ALIAS        -10  /* an output overlaps an input it may not alias */
 #define DRAG_ERR_PLAN         -11  /* invalid batched plan or block table */
 #define DRAG_ERR_STEPS        -12  /* n_steps < 0 (drag_expm_steps) */
+#define DRAG_ERR_SCRATCH      -13  /* the batch's tables exceed the static buffer
+                                      (drag_expm_apply_batched_static) */
 #define DRAG_ERR_HIP          -20  /* the HIP runtime reported an error */
 
 /* per-cell bits of the sticky device status word */
@@ -294,6 +296,36 @@ int drag_plan_set_config(drag_plan *plan, int32_t lane_max, int32_t mfma_mode);
  * k_max = k_max[N_b - 1] and the same mapping. */
 int drag_plan_k_max(const drag_plan *plan, int32_t *k_max);
 int drag_plan_destroy(drag_plan *plan);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batched
+ * update of `desc` without a plan, allocating nothing.  The blocks are laid
+ * out as drag_plan_offsets reports for a plan of the same desc.  The result
+ * is bit for bit that of drag_expm_apply_batched on such a plan pinned to
+ * drag_plan_set_config(plan, 10, DRAG_MFMA_PER_N) (one lane per cell to 8
+ * species, two lanes per cell for 9 and 10, one MFMA grid per species count
+ * above), every block with the Taylor cap desc->k_max (DRAG_K_AUTO: the
+ * cap drag_get_k_max gives its species count; no tuning).
+ *
+ * The block offsets and work items (16 bytes per block, plus 16 bytes per
+ * 64-cell item of blocks with N_b <= 8, per 32-cell item of blocks with
+ * N_b = 9, 10, and per block above) live in a static device buffer of
+ * DRAG_STATIC_SCRATCH_BYTES that every GPU the library runs on holds until
+ * the process ends; a batch whose tables do not fit returns DRAG_ERR_SCRATCH
+ * before anything is enqueued (4096 blocks of 512 cells take about 0.5 MiB).
+ * Each call copies its tables from host memory into that buffer on `stream`,
+ * then enqueues the kernels on `stream`; it neither synchronises nor creates
+ * streams, events or graphs.  Every call on one GPU shares that GPU's buffer:
+ * calls that overlap on one GPU (different streams, or host threads racing)
+ * overwrite each other's tables, so serialise them (for instance on one
+ * stream).  Calls from several host threads of one process are serialised on
+ * the host.  Errors as drag_expm_apply_batched, plus DRAG_ERR_SCRATCH.
+ */
+#define DRAG_STATIC_SCRATCH_BYTES (1u << 20)
+int drag_expm_apply_batched_static(const drag_batch_desc *desc,
+                                   const double *fields, const double *v_in,
+                                   double *v_out, drag_stream_t stream);
 
 /* ---- status and introspection -------------------------------------------- */
 /* Synchronise `stream`, then read the current device's sticky status word. */

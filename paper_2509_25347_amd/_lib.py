@@ -42,6 +42,8 @@ ERR_NULL_POINTER = -9
 ERR_ALIAS = -10
 ERR_PLAN = -11
 ERR_STEPS = -12
+ERR_SCRATCH = -13
+STATIC_SCRATCH_BYTES = 1 << 20
 ERR_HIP = -20
 
 CELL_BAD_DENSITY = 1
@@ -60,6 +62,7 @@ EXPORTS = [
     "drag_plan_autotune", "drag_plan_config", "drag_plan_set_config", "drag_plan_destroy", "drag_get_status", "drag_clear_status", "drag_status_string",
     "drag_table_row", "drag_select", "drag_set_mapping", "drag_get_mapping",
     "drag_set_k_max", "drag_get_k_max", "drag_plan_k_max", "drag_pade_row",
+    "drag_expm_apply_batched_static",
 ]
 
 
@@ -133,6 +136,8 @@ def lib():
     L.drag_plan_offsets.restype = ctypes.c_int
     L.drag_expm_apply_batched.argtypes = [vp, vp, vp, vp, vp]
     L.drag_expm_apply_batched.restype = ctypes.c_int
+    L.drag_expm_apply_batched_static.argtypes = [P(DragBatchDesc), vp, vp, vp, vp]
+    L.drag_expm_apply_batched_static.restype = ctypes.c_int
     L.drag_plan_autotune.argtypes = [vp, vp, vp, vp, vp, P(i32)]
     L.drag_plan_autotune.restype = ctypes.c_int
     L.drag_rk1_apply.argtypes = [P(DragDesc), vp, vp, vp, vp, vp, vp]

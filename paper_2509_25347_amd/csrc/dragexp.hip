@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "../../include/dragexp.h"
@@ -721,6 +722,99 @@ static int plan_capture(drag_plan* P, int lmax, int mode, const double* fields,
   return DRAG_OK;
 }
 
+// ---- the batched update without allocation ------------------------------------
+// A fixed device buffer per GPU (file scope, so the code object reserves it on
+// every device the library loads on, until the process ends) holds the block
+// offsets and the work items that drag_plan_batched would allocate; the host
+// builds them in a fixed host buffer and copies them on the caller's stream.
+// In host code `scratch` names a host-side stand-in: the device address comes
+// from hipGetSymbolAddress, once per device, and only that address is used.
+constexpr size_t kStaticScratchBytes = DRAG_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kStaticLaneMax = 10;  // the configuration the static call runs
+constexpr int kMaxDevices = 64;
+
+static std::mutex g_static_mu;  // one static call at a time per process (host buffer)
+static void* g_scratch_dev[kMaxDevices] = {};
+alignas(256) static unsigned char g_scratch_host[kStaticScratchBytes];
+
+// Device address of this device's scratch array (resolved at the first call
+// on the device, with the device current).
+static int scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return DRAG_ERR_HIP;
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DRAG_ERR_HIP;
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = (unsigned char*)g_scratch_dev[dev];
+  return DRAG_OK;
+}
+
+// Byte layout of the tables in the scratch buffer for one batch: field and
+// velocity offsets [n_blocks] each, then the items of each lane-mapped N
+// (64-cell items to 8 species, 32-cell pair items above) and each MFMA N
+// (whole blocks), every table 16-byte aligned.
+struct StaticLayout {
+  size_t off_field = 0, off_v = 0, off_lane[kPairMaxN + 1] = {}, off_wave[kMaxSpecies + 1] = {};
+  int n_lane[kPairMaxN + 1] = {}, n_wave[kMaxSpecies + 1] = {};
+  size_t bytes = 0;
+};
+
+static StaticLayout static_layout(const drag_batch_desc* bd) {
+  StaticLayout L;
+  const int bc = bd->block_cells;
+  for (int b = 0; b < bd->n_blocks; ++b) {
+    const int n = bd->n_species[b];
+    if (n <= kStaticLaneMax) L.n_lane[n] += (bc + (n <= kLaneMaxN ? 63 : 31)) / (n <= kLaneMaxN ? 64 : 32);
+    else L.n_wave[n] += 1;
+  }
+  size_t at = 0;
+  L.off_field = at;
+  at += sizeof(int64_t) * (size_t)bd->n_blocks;
+  L.off_v = at;
+  at += sizeof(int64_t) * (size_t)bd->n_blocks;
+  for (int n = 1; n <= kStaticLaneMax; ++n) {
+    L.off_lane[n] = at;
+    at += sizeof(BatchItem) * (size_t)L.n_lane[n];
+  }
+  for (int n = kStaticLaneMax + 1; n <= kMaxSpecies; ++n) {
+    L.off_wave[n] = at;
+    at += sizeof(BatchItem) * (size_t)L.n_wave[n];
+  }
+  L.bytes = at;
+  return L;
+}
+
+// Fill the host buffer with the tables of static_layout (same items, in the
+// same order, as the plan's configuration (kStaticLaneMax, per-N grids)).
+static void static_tables(const drag_batch_desc* bd, const StaticLayout& L, unsigned char* host,
+                          int64_t* fields_total, int64_t* v_total) {
+  int64_t* fo = (int64_t*)(host + L.off_field);
+  int64_t* vo = (int64_t*)(host + L.off_v);
+  const int64_t bc = bd->block_cells, D = bd->n_dim;
+  int64_t f = 0, v = 0;
+  int fill_lane[kPairMaxN + 1] = {}, fill_wave[kMaxSpecies + 1] = {};
+  for (int b = 0; b < bd->n_blocks; ++b) {
+    const int n = bd->n_species[b];
+    fo[b] = f;
+    vo[b] = v;
+    f += bc * (1 + 2 * n);
+    v += bc * D * (n + 1);
+    if (n <= kStaticLaneMax) {
+      BatchItem* it = (BatchItem*)(host + L.off_lane[n]);
+      const int step = n <= kLaneMaxN ? 64 : 32;
+      for (int first = 0; first < bd->block_cells; first += step)
+        it[fill_lane[n]++] = BatchItem{b, n, first, std::min(step, bd->block_cells - first)};
+    } else {
+      BatchItem* it = (BatchItem*)(host + L.off_wave[n]);
+      it[fill_wave[n]++] = BatchItem{b, n, 0, bd->block_cells};
+    }
+  }
+  *fields_total = f;
+  *v_total = v;
+}
+
 }  // namespace dragexp
 
 using namespace dragexp;
@@ -1068,6 +1162,59 @@ int drag_plan_destroy(drag_plan* P) {
   return DRAG_OK;
 }
 
+int drag_expm_apply_batched_static(const drag_batch_desc* bd, const double* fields,
+                                   const double* v_in, double* v_out, drag_stream_t stream) {
+  if (!bd) return DRAG_ERR_NULL_DESC;
+  if (bd->n_blocks < 1 || bd->block_cells < 1 || !bd->n_species) return DRAG_ERR_PLAN;
+  if (bd->n_dim < 1 || bd->n_dim > 3) return DRAG_ERR_N_DIM;
+  if (!(bd->dt >= 0.0) || !isfinite(bd->dt)) return DRAG_ERR_DT;
+  if (bd->k_max < DRAG_K_AUTO || bd->k_max > 9) return DRAG_ERR_K_MAX;
+  if (bd->option < 0 || bd->option > 2) return DRAG_ERR_OPTION;
+  for (int b = 0; b < bd->n_blocks; ++b)
+    if (bd->n_species[b] < 1 || bd->n_species[b] > kMaxSpecies) return DRAG_ERR_N_SPECIES;
+  if (!fields || !v_in || !v_out) return DRAG_ERR_NULL_POINTER;
+  const StaticLayout L = static_layout(bd);
+  if (L.bytes > kStaticScratchBytes) return DRAG_ERR_SCRATCH;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  int64_t fields_total = 0, v_total = 0;
+  static_tables(bd, L, g_scratch_host, &fields_total, &v_total);
+  const Range rf{(uintptr_t)fields, (uintptr_t)(fields + fields_total)};
+  const Range ri{(uintptr_t)v_in, (uintptr_t)(v_in + v_total)};
+  const Range ro{(uintptr_t)v_out, (uintptr_t)(v_out + v_total)};
+  if (overlap(ro, rf)) return DRAG_ERR_ALIAS;
+  if ((const double*)v_out != v_in && overlap(ro, ri)) return DRAG_ERR_ALIAS;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DRAG_ERR_HIP;
+  unsigned char* base = nullptr;
+  int rc = scratch_address(dev, &base);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  // a copy from pageable host memory: the runtime has read the host buffer
+  // when the call returns, so the buffer may be refilled by the next call
+  rc = hip_status(hipMemcpyAsync(base, g_scratch_host, L.bytes, hipMemcpyHostToDevice, st));
+  if (rc) return rc;
+  BatchArgs B{nullptr, (const int64_t*)(base + L.off_field), (const int64_t*)(base + L.off_v),
+              fields, v_in, v_out, nullptr, 0, bd->block_cells, bd->n_dim, bd->option, bd->dt,
+              {}};
+  for (int n = 0; n <= kMaxSpecies; ++n) B.k_max_n[n] = n ? k_for(bd->k_max, n) : 0;
+  for (int n = 1; n <= kStaticLaneMax; ++n) {
+    if (L.n_lane[n] == 0) continue;
+    BatchArgs X = B;
+    X.items = (const BatchItem*)(base + L.off_lane[n]);
+    X.n_items = L.n_lane[n];
+    batched_lane(n, X, st);
+  }
+  const int gpb = (bd->block_cells + 15) / 16;
+  for (int n = kMaxSpecies; n > kStaticLaneMax; --n) {
+    if (L.n_wave[n] == 0) continue;
+    BatchArgs X = B;
+    X.items = (const BatchItem*)(base + L.off_wave[n]);
+    X.n_items = L.n_wave[n];
+    batched_wave_n(n, X, gpb, st);
+  }
+  return hip_status(hipGetLastError());
+}
+
 int drag_get_status(drag_stream_t stream, int32_t* host_status) {
   if (!host_status) return DRAG_ERR_NULL_POINTER;
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
@@ -1092,6 +1239,7 @@ const char* drag_status_string(int code) {
     case DRAG_ERR_N_SPECIES: return "n_species outside [1, 16] (or [1, 32] for the forward calls)";
     case DRAG_ERR_N_DIM: return "n_dim outside [1, 3]";
     case DRAG_ERR_STEPS: return "n_steps < 0, or the history would overflow 64-bit offsets";
+    case DRAG_ERR_SCRATCH: return "the batch's block tables exceed the static scratch buffer";
     case DRAG_ERR_LD: return "ld < n_cells or ld too large";
     case DRAG_ERR_DT: return "dt is NaN, infinite or negative";
     case DRAG_ERR_K_MAX: return "k_max outside [0 (auto), 9]";

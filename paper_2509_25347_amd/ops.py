@@ -249,6 +249,34 @@ def drag_expm(rho_g, rho_d, t_stop, v, dt, k_max=9, option=2):
     return DragExpm.apply(rho_g, rho_d, t_stop, v, dt, k_max, option)
 
 
+def expm_apply_batched_static(n_species, block_cells, n_dim, dt, fields, v_in, v_out=None,
+                              k_max=9, option=2, stream=None):
+    """The batched update without a plan and without allocation in the
+    library (drag_expm_apply_batched_static): the block tables go to a static
+    device buffer of the library.  Buffers laid out as BatchPlan's for the
+    same blocks; ``v_out`` may be ``v_in``.  (Allocating ``v_out`` here when
+    it is None is the binding's convenience, not the library's.)"""
+    for x, nm in ((fields, "fields"), (v_in, "v_in")):
+        _require(x, nm)
+    if v_out is None:
+        v_out = torch.empty_like(v_in)
+    _require(v_out, "v_out")
+    ns = [int(x) for x in n_species]
+    arr = (ctypes.c_int32 * len(ns))(*ns)
+    desc = _lib.DragBatchDesc(len(ns), int(block_cells), int(n_dim), int(k_max), int(option),
+                              float(dt), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)))
+    bc, D = int(block_cells), int(n_dim)
+    f_need = sum(bc * (1 + 2 * n) for n in ns)
+    v_need = sum(bc * D * (n + 1) for n in ns)
+    if fields.numel() < f_need or v_in.numel() < v_need or v_out.numel() < v_need:
+        raise ValueError("buffers smaller than the batch's layout")
+    _lib.check(_lib.lib().drag_expm_apply_batched_static(ctypes.byref(desc), _ptr(fields),
+                                                         _ptr(v_in), _ptr(v_out),
+                                                         _stream_ptr(stream)),
+               "drag_expm_apply_batched_static")
+    return v_out
+
+
 class BatchPlan:
     """AMR-style blocks with uneven species counts in one graph launch
     (drag_plan_batched / drag_expm_apply_batched).

@@ -1,0 +1,80 @@
+"""The batched update without allocation (drag_expm_apply_batched_static),
+called through the C ABI: bit for bit the plan's result in the same launch
+configuration (lane bound 10, one MFMA grid per species count), on two calls
+in a row, the second with a smaller batch (the shared static buffer keeps the
+first call's tables, which the second must not read past); in place; a batch
+whose tables do not fit is refused before anything is enqueued."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2509_25347_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_25347_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+def _plan_result(ops, batch, bc, D, k_max, dev):
+    plan = ops.BatchPlan(batch["n_species"], bc, D, batch["dt"], k_max=k_max)
+    try:
+        plan.set_config(10, "per_n")
+        fields, v = plan.pack(batch["blocks"], dev)
+        out = plan.apply(fields, v)
+        torch.cuda.synchronize()
+        return fields, v, out.clone()
+    finally:
+        plan.close()
+
+
+def _static_call(_lib, batch, bc, D, k_max, fields, v_in, v_out):
+    ns = [int(x) for x in batch["n_species"]]
+    arr = (ctypes.c_int32 * len(ns))(*ns)
+    desc = _lib.DragBatchDesc(len(ns), bc, D, k_max, 2, float(batch["dt"]),
+                              ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)))
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return _lib.lib().drag_expm_apply_batched_static(
+        ctypes.byref(desc), ctypes.c_void_p(fields.data_ptr()), ctypes.c_void_p(v_in.data_ptr()),
+        ctypes.c_void_p(v_out.data_ptr()), stream)
+
+
+def test_static_batched_matches_the_plan_twice(dev):
+    from paper_2509_25347_amd import _lib, ops
+    cases = [(W.make_batched(n_blocks=300, block_cells=100, D=3, seed_cfg=61), 100, 3, 9),
+             (W.make_batched(n_blocks=37, block_cells=70, D=2, seed_cfg=62), 70, 2, _lib.K_AUTO)]
+    for k, (batch, bc, D, K) in enumerate(cases):
+        print(f"static batched call {k}: {len(batch['blocks'])} blocks x {bc} cells, D={D}",
+              flush=True)
+        fields, v, ref = _plan_result(ops, batch, bc, D, K, dev)
+        out = torch.full_like(v, float("nan"))
+        rc = _static_call(_lib, batch, bc, D, K, fields, v, out)
+        assert rc == _lib.OK, rc
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), k
+        # in place
+        vv = v.clone()
+        assert _static_call(_lib, batch, bc, D, K, fields, vv, vv) == _lib.OK
+        torch.cuda.synchronize()
+        assert torch.equal(vv, ref), k
+
+
+def test_static_batched_refuses_oversized_tables(dev):
+    from paper_2509_25347_amd import _lib
+    # 30000 one-species blocks of 65 cells: 2 items each -> 16 * (30000 + 60000) B > 1 MiB
+    n = 30000
+    batch = dict(n_species=np.ones(n, dtype=np.int32), dt=1.0)
+    fields = torch.zeros(n * 65 * 3, dtype=torch.float64, device=dev)
+    v = torch.zeros(n * 65 * 2, dtype=torch.float64, device=dev)
+    out = torch.full_like(v, 7.0)
+    assert _static_call(_lib, batch, 65, 1, 9, fields, v, out) == _lib.ERR_SCRATCH
+    torch.cuda.synchronize()
+    assert (out == 7.0).all()
