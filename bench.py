@@ -324,18 +324,40 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def _time(torch, fn, steps, warmup):
+def _time(torch, fn, steps, warmup, chunks=1):
+    """ms per call: HIP events around `steps` calls after `warmup`; with
+    chunks > 1 the median over that many such runs (the per-launch time of
+    the sub-millisecond kernels wanders by about 10 % between runs on these
+    boxes, with no gaps between the kernels in their traces)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        fn()
-    e1.record()
+    runs = []
+    for _ in range(chunks):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1) / steps)
+    return float(np.median(runs))
+
+
+def _interleaved(torch, fns, steps, warmup, rounds=5):
+    """Median ms per call of each function, timed in alternation (`rounds`
+    rounds of `steps` calls each) so that a ratio between them does not
+    carry the drift of the GPU's clock from one run to the next."""
+    for fn in fns:
+        for _ in range(warmup):
+            fn()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    runs = [[] for _ in fns]
+    for _ in range(rounds):
+        for i, fn in enumerate(fns):
+            runs[i].append(_time(torch, fn, steps, 0))
+    return [float(np.median(r)) for r in runs]
 
 
 def _graph_time(torch, fn, launches=20, replays=20):
@@ -432,7 +454,7 @@ def config_report(torch, ops, _lib, workloads, dev):
         T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
         o = torch.empty_like(T["v"])
         ms = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
-                                                 d["dt"], out=o), 50, 5)
+                                                 d["dt"], out=o), 50, 5, chunks=5)
         got = o.cpu().numpy()
         _, _, _, kk, mm, ss = ops.build(T["rho_g"], T["rho_d"], T["t_stop"], d["dt"])
         kk, mm, ss = (x.cpu().numpy() for x in (kk, mm, ss))
@@ -450,14 +472,20 @@ def config_report(torch, ops, _lib, workloads, dev):
                 torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
                                               d["dt"], out=o))
         ms_auto = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
-                                                      d["dt"], k_max=_lib.K_AUTO, out=o), 50, 5)
+                                                      d["dt"], k_max=_lib.K_AUTO, out=o), 50, 5,
+                        chunks=5)
         row["taylor_cap_tuned"] = {"k_max": _lib.get_k_max(N), "ms": ms_auto,
                                    "cells_per_s": C / (ms_auto * 1e-3), "speedup_vs_k9": ms / ms_auto}
         if cfg == 5:
             dd = workloads.make(name, with_weights=True)
             Tw = torch.from_numpy(dd["w"]).to(dev)
-            row["fwd_bwd_ms"] = _time(torch, lambda: ops.expm_apply_backward(
-                T["rho_g"], T["rho_d"], T["t_stop"], T["v"], Tw, d["dt"]), 20, 3)
+            tf, tb = _interleaved(torch, [
+                lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"], out=o),
+                lambda: ops.expm_apply_backward(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], Tw,
+                                                d["dt"])], 20, 3)
+            row["fwd_bwd_ms"] = tb
+            row["fwd_ms_alternating"] = tf
+            row["fwd_bwd_over_fwd"] = tb / tf
         out[f"config{cfg}"] = row
     # config 4: the batched launch; the oracle on the first 32 blocks
     batch = workloads.make_batched()
@@ -799,12 +827,13 @@ def adjoint_measurement(torch, ops, workloads, dev):
     dd = workloads.make("n8_adjoint_3d", with_weights=True)
     TT = {k: torch.from_numpy(dd[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v", "w")}
     oo = torch.empty_like(TT["v"])
-    tf = _time(torch, lambda: ops.expm_apply(TT["rho_g"], TT["rho_d"], TT["t_stop"], TT["v"],
-                                             dd["dt"], out=oo), 20, 3)
-    tb = _time(torch, lambda: ops.expm_apply_backward(TT["rho_g"], TT["rho_d"], TT["t_stop"],
-                                                      TT["v"], TT["w"], dd["dt"]), 10, 2)
+    tf, tb = _interleaved(torch, [
+        lambda: ops.expm_apply(TT["rho_g"], TT["rho_d"], TT["t_stop"], TT["v"], dd["dt"], out=oo),
+        lambda: ops.expm_apply_backward(TT["rho_g"], TT["rho_d"], TT["t_stop"], TT["v"],
+                                        TT["w"], dd["dt"])], 10, 3)
     return {"workload": "n8_adjoint_3d", "n_cells": int(dd["rho_g"].shape[0]),
-            "fwd_ms": tf, "fwd_bwd_ms": tb, "fwd_bwd_over_fwd": tb / tf}
+            "fwd_ms": tf, "fwd_bwd_ms": tb, "fwd_bwd_over_fwd": tb / tf,
+            "timing": "medians of 5 alternating runs of 10 calls each"}
 
 
 def batched_measurement(torch, ops, workloads, dev):
@@ -832,14 +861,12 @@ def batched_measurement(torch, ops, workloads, dev):
         plan.autotune(fields, v, out)
         lane_max, mfma_mode = plan.config()
         ks = plan.k_max()
-        tb = _time(torch, lambda: plan.apply(fields, v, out), 10, 2)
-
         def plain():
             for N, cat, o in per:
                 ops.expm_apply(cat["rho_g"], cat["rho_d"], cat["t_stop"], cat["v"], batch["dt"],
                                k_max=ks[N - 1], out=o)
 
-        tp = _time(torch, plain, 10, 2)
+        tb, tp = _interleaved(torch, [lambda: plan.apply(fields, v, out), plain], 5, 2)
         plan.close()
         row = {"batched_ms": tb, "plain_per_n_ms": tp, "batched_over_plain": tb / tp,
                "batched_cells_per_s": cells / (tb * 1e-3), "lane_max": lane_max,

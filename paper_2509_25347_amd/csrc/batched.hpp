@@ -135,6 +135,8 @@ __global__ void __launch_bounds__(256) k_batched_lane(BatchArgs B) {
 // One 32-cell item per wavefront, two lanes per cell (N = 9..12).
 template <int N>
 __global__ void __launch_bounds__(256, pair_fwd_min_waves<N>()) k_batched_pair(BatchArgs B) {
+  constexpr int kStride = 128 + 2;  // 32 pairs per wavefront, 4 wavefronts
+  __shared__ double vsm[3 * (N + 1) * kStride];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int idx = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
   if (idx >= B.n_items) return;  // uniform over the wavefront
@@ -143,7 +145,8 @@ __global__ void __launch_bounds__(256, pair_fwd_min_waves<N>()) k_batched_pair(B
   const int p = lane >> 1;
   const bool active = p < it.count;
   const int64_t c = (int64_t)it.first + p;
-  pair_forward_cell<N>(A, c, active ? c : it.first, active, lane & 1);
+  pair_forward_cell<N>(A, c, active ? c : it.first, active, lane & 1, vsm + (threadIdx.x >> 1),
+                       kStride);
 }
 
 }  // namespace dragexp

@@ -55,11 +55,15 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
   constexpr int W2 = 2 * H;       // padded width
   constexpr int kCells = 128;     // cells per workgroup (two lanes each)
   // per cell, global column order, zero padded: ubar[3][W2], dv[3][W2], a[W2], e[W2],
+  // then per component the gas velocity, the gas weight w_0 and W = sum_j w_j (the
+  // output stage rebuilds v and w from these instead of reading them again),
   // stored entry-major (entry x of pair pl at sm[x * kStride + pl]): the pairs of a
   // wavefront read consecutive doubles, and the two lanes of a pair, whose entries
   // lie H apart, fall on the other half of the banks (kStride = 2 mod 4)
   constexpr int kStride = kCells + 2;
-  __shared__ double sm[8 * W2 * kStride];
+  constexpr int kGas = 8 * W2;  // v_0[3], w_0[3], W[3]
+  constexpr bool kRebuild = N <= 8;
+  __shared__ double sm[(kGas + 9) * kStride];
 
   const int bid = blockIdx.x;
   const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
@@ -127,6 +131,9 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
         my[(d * W2 + k) * kStride] = k < N ? w[k + 1] - W * C.e[k < N ? k : 0] / C.sigma : 0.0;
         my[((3 + d) * W2 + k) * kStride] = k < N ? v[k + 1] - v[0] : 0.0;
       }
+      my[(kGas + d) * kStride] = v[0];
+      my[(kGas + 3 + d) * kStride] = w[0];
+      my[(kGas + 6 + d) * kStride] = W;
     }
 #pragma unroll
     for (int k = 0; k < W2; ++k) {
@@ -302,25 +309,32 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
     const double eu = pair_sum(eu_own, h);
     const double d0 = -eu * rsig;
     const double zt_sum = pair_sum(zt_own, h);
-    double W = 0.0;
+    // v and w of this cell: at N <= 8 rebuilt from LDS (v_k = v_0 + dv_k,
+    // w_k = ubar_k + W e_k / sigma, each within a rounding of the input) rather
+    // than read again from memory after the squarings; at N = 9, 10 the
+    // rebuild's registers would spill, so those read them again
+    const double W = my[(kGas + 6 + d) * kStride];
     const int64_t base = (int64_t)(d * n1) * ld + c;
-#pragma unroll
-    for (int j = 0; j <= N; ++j) W += A.w[(int64_t)(d * n1 + j) * ld + cc];
 #pragma unroll
     for (int r = 0; r < H; ++r) ge_dir[r] = fma(-d0 - u[r], W * rsig, ge_dir[r]);
     if (active) {
+      const double v0 = kRebuild ? my[(kGas + d) * kStride] : A.v_in[base];
+      const double w0 = kRebuild ? my[(kGas + 3 + d) * kStride] : A.w[base];
 #pragma unroll
       for (int r = 0; r < H; ++r) {
         const int k = h * H + r;
         if (k < N) {
           const int64_t idx = base + (int64_t)(1 + k) * ld;
-          if (A.v_out) A.v_out[idx] = bad ? qnan : A.v_in[idx] + (d0 + u[r]);
-          if (A.g_v) A.g_v[idx] = bad ? qnan : A.w[idx] + zt[r];
+          const double e_k = my[(7 * W2 + k) * kStride];
+          const double vk = kRebuild ? v0 + dv[r] : A.v_in[idx];
+          const double wk = kRebuild ? ub[r] + W * e_k / sigma : A.w[idx];
+          if (A.v_out) A.v_out[idx] = bad ? qnan : vk + (d0 + u[r]);
+          if (A.g_v) A.g_v[idx] = bad ? qnan : wk + zt[r];
         }
       }
       if (h == 0) {
-        if (A.v_out) A.v_out[base] = bad ? qnan : A.v_in[base] + d0;
-        if (A.g_v) A.g_v[base] = bad ? qnan : A.w[base] - zt_sum;
+        if (A.v_out) A.v_out[base] = bad ? qnan : v0 + d0;
+        if (A.g_v) A.g_v[base] = bad ? qnan : w0 - zt_sum;
       }
     }
   }
@@ -369,10 +383,14 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
 // The forward update of cell c by the pair of lanes (h = 0, 1) that share
 // it.  Both lanes of every pair of the wavefront must call it together (DPP
 // swaps, wavefront-wide maxima of m and s); a spare pair passes any valid
-// cell as cc, computes on it and stores nothing.
+// cell as cc, computes on it and stores nothing.  vs is the pair's LDS
+// staging of its velocities (entry d (N + 1) + j at vs[x * vstride], 3 (N + 1)
+// entries): lane 0 reads them once, for the finiteness check, and the apply
+// stage takes them from there (read again from memory after the squarings,
+// they had been evicted from L2: 1.25-1.32x the algorithmic reads at N = 9, 10).
 template <int N>
 __device__ __forceinline__ void pair_forward_cell(const CellArgs& A, int64_t c, int64_t cc,
-                                                  bool active, int h) {
+                                                  bool active, int h, double* vs, int vstride) {
   constexpr int H = (N + 1) / 2;
   constexpr int W2 = 2 * H;
   const int64_t ld = A.ld;
@@ -382,11 +400,19 @@ __device__ __forceinline__ void pair_forward_cell(const CellArgs& A, int64_t c, 
 
   LaneCell<N> C;
   lane_setup<N>(C, A.rho_g, A.rho_d, A.t_stop, ld, cc, A.dt, A.k_max, A.option);
-  bool vfin = true;
-  for (int d = 0; d < D; ++d) {
+  double fin = 1.0;
+  if (h == 0) {
+    for (int d = 0; d < D; ++d) {
 #pragma unroll
-    for (int j = 0; j <= N; ++j) vfin = vfin && isfinite(A.v_in[(int64_t)(d * n1 + j) * ld + cc]);
+      for (int j = 0; j <= N; ++j) {
+        const double x = A.v_in[(int64_t)(d * n1 + j) * ld + cc];
+        vs[(d * n1 + j) * vstride] = x;
+        fin = isfinite(x) ? fin : 0.0;
+      }
+    }
   }
+  const double fin_pair = pair_swap(fin);  // lane 1 takes lane 0's verdict
+  const bool vfin = (h == 0 ? fin : fin_pair) != 0.0;
   if (!vfin && !C.bad) C.bad = kBadVelocity;
   const int s = C.kms.s, m = C.kms.m;
 
@@ -472,12 +498,12 @@ __device__ __forceinline__ void pair_forward_cell(const CellArgs& A, int64_t c, 
   const double qnan = __builtin_nan("");
   for (int d = 0; d < D; ++d) {
     const int64_t base = (int64_t)(d * n1) * ld;
-    const double v0 = A.v_in[base + cc];
+    const double v0 = vs[(d * n1) * vstride];
     double dv[W2];
 #pragma unroll
     for (int k = 0; k < W2; ++k) {
-      const int g = gcol(k);  // a run-time row index is fine for memory
-      dv[k] = g < N ? A.v_in[base + (int64_t)(1 + g) * ld + cc] - v0 : 0.0;
+      const int g = gcol(k);  // a run-time row index is fine for LDS
+      dv[k] = g < N ? vs[(d * n1 + 1 + g) * vstride] - v0 : 0.0;
     }
     double u[H], eu_own = 0.0;
 #pragma unroll
@@ -495,7 +521,7 @@ __device__ __forceinline__ void pair_forward_cell(const CellArgs& A, int64_t c, 
         const int k = h * H + r;
         if (k < N) {
           const int64_t idx = base + (int64_t)(1 + k) * ld + c;
-          A.v_out[idx] = C.bad ? qnan : A.v_in[idx] + (d0 + u[r]);
+          A.v_out[idx] = C.bad ? qnan : vs[(d * n1 + 1 + k) * vstride] + (d0 + u[r]);
         }
       }
       if (h == 0) A.v_out[base + c] = C.bad ? qnan : v0 + d0;
@@ -515,11 +541,14 @@ template <int N>
 __global__ void __launch_bounds__(256, pair_fwd_min_waves<N>()) k_forward_pair(CellArgs A,
                                                                               int xcd_blocks) {
   constexpr int kCells = 128;  // cells per workgroup, two lanes each
+  constexpr int kStride = kCells + 2;
+  __shared__ double vsm[3 * (N + 1) * kStride];
   const int bid = blockIdx.x;
   const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
-  const int64_t c = logical * kCells + (threadIdx.x >> 1);
+  const int pl = threadIdx.x >> 1;
+  const int64_t c = logical * kCells + pl;
   const bool active = c < A.n_cells;
-  pair_forward_cell<N>(A, c, active ? c : 0, active, threadIdx.x & 1);
+  pair_forward_cell<N>(A, c, active ? c : 0, active, threadIdx.x & 1, vsm + pl, kStride);
 }
 
 }  // namespace dragexp
