@@ -55,15 +55,17 @@ PS_R = {1: 1, 2: 1, 3: 2, 4: 2, 5: 3, 6: 4, 7: 4, 8: 5, 9: 6}
 
 def executed_flops(k, m, s, N, D, mapping):
     """FP64 flops the library executes per cell.  MFMA kernel: (r-1) Horner
-    products, s squarings and the apply on 16 x 16 tiles (2 * 16^3 each),
-    (q-1) structured powers (4 * 16^2) and the B-bar sums (2 * 16^2 per
-    coefficient, q r of them).  Lane kernel: Horner in the structured matrix
-    (4 N^2 per degree), s squarings (2 N^3) and the apply (2 D N^2)."""
+    products, s squarings and the apply on 16 x 16 tiles with a contraction
+    length of 4 ceil(N / 4) (2 * 16^2 * that each), (q-1) structured powers
+    (4 * 16^2) and the B-bar sums (2 * 16^2 per coefficient, q r of them).
+    Lane kernel: Horner in the structured matrix (4 N^2 per degree), s
+    squarings (2 N^3) and the apply (2 D N^2)."""
     if mapping == "wave":
-        t = 16
+        t, tk = 16, 4 * ((N + 3) // 4)
         q = np.vectorize(PS_Q.get)(k)
         r = np.vectorize(PS_R.get)(k)
-        return (r - 1 + s + 1) * 2.0 * t ** 3 + (q - 1) * 4.0 * t * t + 2.0 * q * r * t * t
+        return ((r - 1 + s + 1) * 2.0 * t * t * tk + (q - 1) * 4.0 * t * t
+                + 2.0 * q * r * t * t)
     return (s * 2.0 * N ** 3 + m * 4.0 * N * N + 2.0 * D * N * N)
 
 
@@ -831,8 +833,20 @@ def adjoint_measurement(torch, ops, workloads, dev):
         lambda: ops.expm_apply(TT["rho_g"], TT["rho_d"], TT["t_stop"], TT["v"], dd["dt"], out=oo),
         lambda: ops.expm_apply_backward(TT["rho_g"], TT["rho_d"], TT["t_stop"], TT["v"],
                                         TT["w"], dd["dt"])], 10, 3)
+    # FMAs per cell of the two as implemented, at the cells' own (m*, s*):
+    # forward = structured Horner (2N^2 + N per degree), Y-form squarings
+    # (N^3 each), apply (D N^2); fused = Horner on Y and dY with the rank-D
+    # direction (4N^2 + 2N + 2D N^2 per degree), three products per squaring
+    # (3 N^3), both applies (2 D N^2)
+    _, _, _, _, mm, ss = ops.build(TT["rho_g"], TT["rho_d"], TT["t_stop"], dd["dt"])
+    m, s = float(mm.double().mean()), float(ss.double().mean())
+    N, D = int(TT["rho_d"].shape[0]), int(TT["v"].shape[0])
+    fma_f = (2 * N * N + N) * m + N ** 3 * s + D * N * N
+    fma_b = (4 * N * N + 2 * N + 2 * D * N * N) * m + 3 * N ** 3 * s + 2 * D * N * N
     return {"workload": "n8_adjoint_3d", "n_cells": int(dd["rho_g"].shape[0]),
             "fwd_ms": tf, "fwd_bwd_ms": tb, "fwd_bwd_over_fwd": tb / tf,
+            "fma_per_cell": {"fwd": fma_f, "fwd_bwd": fma_b, "ratio": fma_b / fma_f,
+                             "mean_m": m, "mean_s": s},
             "timing": "medians of 5 alternating runs of 10 calls each"}
 
 

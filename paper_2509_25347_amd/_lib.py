@@ -12,12 +12,8 @@ import os
 import subprocess
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-ROOT = os.path.dirname(_HERE)
 SO_PATH = os.path.join(_HERE, "libdragexp.so")
 SOURCES = [os.path.join(_HERE, "csrc", "dragexp.hip")]
-HEADERS = [os.path.join(ROOT, "include", "dragexp.h")] + [
-    os.path.join(_HERE, "csrc", f) for f in ("common.hpp", "lane.hpp", "wave.hpp",
-                                              "adjoint.hpp", "batched.hpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -283,7 +283,7 @@ __device__ __forceinline__ v4d mul_Bt(const v4d& X, const double (&nb)[4], const
 // T_m(B) - I and its derivative in the direction dB by the Paterson-Stockmeyer
 // scheme with Q powers: P_p = B P_{p-1} (structured), dP_p = dB P_{p-1} +
 // B dP_{p-1}; Horner F <- Bbar_k + F P_Q, dF <- dBbar_k + dF P_Q + F dP_Q.
-template <int Q>
+template <int Q, int KT = 4>
 __device__ __forceinline__ void bwd_poly(const v4d& Bt, const v4d& dB, const double (&dBA)[4],
                                          const double (&nb)[4], const double (&npb)[4], int r,
                                          double* stage, double* stage2, int g, int j, v4d& F,
@@ -298,7 +298,7 @@ __device__ __forceinline__ void bwd_poly(const v4d& Bt, const v4d& dB, const dou
 #pragma unroll
     for (int t = 0; t < 4; ++t) Bp[t] = P[p - 1][t];
     P[p] = mul_Bt(P[p - 1], nb, npb);
-    dP[p] = mma16(dBA, Bp, mul_Bt(dP[p - 1], nb, npb));
+    dP[p] = mma_k<KT>(dBA, Bp, mul_Bt(dP[p - 1], nb, npb));
   }
   double Bq[4], dBq[4];
 #pragma unroll
@@ -322,13 +322,15 @@ __device__ __forceinline__ void bwd_poly(const v4d& Bt, const v4d& dB, const dou
     double AF[4], AdF[4];
     stage_tile(stage, g, j, F);
     stage_tile(stage2, g, j, dF);
-    load_a_ops(stage, g, j, AF);
-    load_a_ops(stage2, g, j, AdF);
-    dF = mma16(AF, dBq, mma16(AdF, Bq, comb(dP, k)));
-    F = mma16(AF, Bq, comb(P, k));
+    load_a_ops<KT>(stage, g, j, AF);
+    load_a_ops<KT>(stage2, g, j, AdF);
+    dF = mma_k<KT>(AF, dBq, mma_k<KT>(AdF, Bq, comb(dP, k)));
+    F = mma_k<KT>(AF, Bq, comb(P, k));
   }
 }
 
+// KT: MFMA steps per product (mfma_steps(N) for a compile-time N, else 4).
+template <int KT = 4>
 __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int N, int64_t c0,
                                                    int lane, double* lds) {
   const int g = lane >> 4, j = lane & 15;
@@ -421,7 +423,7 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
     for (int v = 0; v < 4; ++v) dB[v] = ldexp(dB[v], -s);
     double dBA[4];
     stage_tile(stage2, g, j, dB);
-    load_a_ops(stage2, g, j, dBA);
+    load_a_ops<KT>(stage2, g, j, dBA);
 
     // B = M^T: B[row][col] = -b_row [row == col] - pb_row
     v4d Bt;
@@ -432,11 +434,11 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
     }
     v4d F, dF;
     switch (q) {  // uniform; one code path per power count
-      case 1: bwd_poly<1>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
-      case 2: bwd_poly<2>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
-      case 3: bwd_poly<3>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
-      case 4: bwd_poly<4>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
-      default: bwd_poly<5>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+      case 1: bwd_poly<1, KT>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+      case 2: bwd_poly<2, KT>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+      case 3: bwd_poly<3, KT>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+      case 4: bwd_poly<4, KT>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
+      default: bwd_poly<5, KT>(Bt, dB, dBA, nb, npb, r, stage, stage2, g, j, F, dF); break;
     }
 
     // squarings with the Frechet recurrence
@@ -452,10 +454,10 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
       stage_tile(stage2, g, j, dY);
       if (g == 0) atomicAdd(stage + diag_slot, 2.0);
       __builtin_amdgcn_wave_barrier();
-      load_a_ops(stage, g, j, AY);    // Y + 2I
-      load_a_ops(stage2, g, j, AdY);  // dY
-      dY = mma16(AdY, BY, mma16(AY, BdY, zero4));
-      Y = mma16(AY, BY, zero4);
+      load_a_ops<KT>(stage, g, j, AY);    // Y + 2I
+      load_a_ops<KT>(stage2, g, j, AdY);  // dY
+      dY = mma_k<KT>(AdY, BY, mma_k<KT>(AY, BdY, zero4));
+      Y = mma_k<KT>(AY, BY, zero4);
     }
 
     // Y = Z^T, dY = dL/dAt.  u_c = Z dv_c = (dV^T Y)[c];  Z^T ubar_c = (Ubar^T Z)[c]
@@ -463,7 +465,7 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
 #pragma unroll
     for (int t = 0; t < 4; ++t) YB[t] = Y[t];
     stage_tile(stage, g, j, Y);
-    load_a_ops(stage, g, j, ZB);  // Z = Y^T as the B operand
+    load_a_ops<KT>(stage, g, j, ZB);  // Z = Y^T as the B operand
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       // A operand rows are components: lane (g, i) takes component i, species 4t+g
@@ -472,8 +474,8 @@ __device__ __forceinline__ void wave_backward_quad(const BackArgs& A, const int 
       DvA[t] = (j < D) ? a1 : 0.0;
       UbA[t] = (j < D) ? a2 : 0.0;
     }
-    const v4d Um = mma16(DvA, YB, zero4);  // lane (g, j) [0]: u_g[j]
-    const v4d Vm = mma16(UbA, ZB, zero4);  // lane (g, j) [0]: (Z^T ubar_g)_j
+    const v4d Um = mma_k<KT>(DvA, YB, zero4);  // lane (g, j) [0]: u_g[j]
+    const v4d Vm = mma_k<KT>(UbA, ZB, zero4);  // lane (g, j) [0]: (Z^T ubar_g)_j
     const double u = cj ? Um[0] : 0.0;
     const double zt = cj ? Vm[0] : 0.0;
     const double eu = row_chain(0.0, ej * u, N);
@@ -529,7 +531,7 @@ __global__ void __launch_bounds__(256, 3) k_backward_wave(BackArgs A, int xcd_bl
   const int64_t logical = (int64_t)(bid & 7) * xcd_blocks + (bid >> 3);
   const int64_t c0 = (logical * 4 + w) * 4;
   if (c0 >= A.n_cells) return;  // uniform over the wavefront
-  wave_backward_quad(A, N, c0, lane, lds + w * (kQuadDoubles + kStageDoubles));
+  wave_backward_quad<mfma_steps(N)>(A, N, c0, lane, lds + w * (kQuadDoubles + kStageDoubles));
 }
 
 // ---- N <= 8: the block form on one 16 x 16 tile -------------------------------

@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256, METHOD == kStageTaylor ? 5 : 4)
   const int n = NC > 0 ? NC : it.n;
   const int c0 = g0 + 4 * w;
   if (c0 < B.block_cells)
-    wave_forward_quad<METHOD>(A, n, c0, lane, lds + w * kQuadDoubles, false);
+    wave_forward_quad<METHOD, mfma_steps(NC)>(A, n, c0, lane, lds + w * kQuadDoubles, false);
   __syncthreads();
   group_store(A, n, g0, lds);
 }

@@ -141,12 +141,14 @@ static int resident_blocks(const void* kernel, std::atomic<int>& per_cu, int* ou
 // slower at N = 5, 6).  The one-shot kernel issues all of a cell's loads up
 // front except at N = 3, where the velocities' registers would cut the
 // resident wavefronts from 8 to 5 (interleaved timings, 2^18-2^20 cells).
+// The batched lane grids keep the plain form: each wavefront takes one item,
+// and issuing every load up front there was 0.5 % slower per replay.
 constexpr int kLaneStreamMinN = 7;
 constexpr bool lane_early_loads(int n) { return n != 3 && n < kLaneStreamMinN; }
 
-// The raw buffer loads of the one-lane kernels address each input array with
+// The raw buffer accesses of the one-lane kernels address each array with
 // 32-bit byte offsets: its last byte, 8 ((rows - 1) ld + n_cells), must lie
-// below 2^32 (the velocities, D (N + 1) rows, are the largest array).
+// below 2^32 (the velocities in and out, D (N + 1) rows, are the largest).
 template <int N>
 static bool lane_buffers_fit(const CellArgs& A) {
   const int64_t rows = (int64_t)A.n_dim * (N + 1);

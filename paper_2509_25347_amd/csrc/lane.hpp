@@ -204,6 +204,41 @@ __device__ __forceinline__ void lane_expm(double (&Z)[N][N], const LaneCell<N>& 
   }
 }
 
+// Raw buffer accesses for the one-lane kernels' inputs and outputs: one
+// scalar resource per array (per velocity component), the row as a
+// wave-uniform SGPR offset j * row shared by every array, and the cell as
+// one 32-bit lane offset shared by every access of the cell.  Prefetching a
+// cell's inputs then holds one address register, and the 2N + 1 + D (N + 1)
+// rows cost a few resources and N + 1 row offsets instead of a resource or a
+// 64-bit address per row (a resource per row needed four SGPRs each: 176 at
+// N = 8, which the compiler spilled).  The resource:
+// stride 0 (raw), num_records = the array's bytes (bit pattern, below 2^32:
+// the host checks 8 ((rows - 1) ld + n_cells) < 2^32), and the CDNA word-3
+// flags for 32-bit untyped data; an offset at or past the end reads 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const double* base, uint32_t bytes) {
+  constexpr int kRawBufferFlags = 0x00020000;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)bytes,
+                                           kRawBufferFlags);
+}
+
+__device__ __forceinline__ double rsrc_at(__amdgpu_buffer_rsrc_t r, uint32_t lane_off,
+                                          uint32_t row_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, row_off, 0));
+}
+
+// ... and the vector store of x at the same kind of address (an offset at or
+// past the end is dropped).
+__device__ __forceinline__ void rsrc_put(__amdgpu_buffer_rsrc_t r, uint32_t lane_off,
+                                         uint32_t row_off, double x) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, lane_off, row_off, 0);
+}
+
+// Bytes of an SoA array of `rows` rows of n_cells cells, leading dimension ld.
+__device__ __forceinline__ uint32_t array_bytes(int64_t rows, const CellArgs& A) {
+  return (uint32_t)(8 * ((rows - 1) * A.ld + A.n_cells));
+}
+
 // v' = v + E v - v for component d of the lane's cell: u = Z dv on the
 // relative velocities, the gas by momentum conservation; NaN for a bad cell.
 template <int N>
@@ -226,11 +261,18 @@ __device__ __forceinline__ void lane_apply_component(const CellArgs& A, const La
   }
   const double d0 = -eu / C.sigma;
   if (active) {
+    // stores through a resource for the component's rows, with the same
+    // scalar row offsets j * row as the loads (rather than a 64-bit address
+    // per row)
+    const uint32_t row = (uint32_t)(8 * A.ld);
+    const __amdgpu_buffer_rsrc_t r =
+        raw_rsrc(A.v_out + (int64_t)d * n1 * A.ld, array_bytes(n1, A));
+    const uint32_t off = (uint32_t)(8 * c);
     const double qnan = __builtin_nan("");
-    A.v_out[(int64_t)(d * n1) * A.ld + c] = C.bad ? qnan : v[0] + d0;
+    rsrc_put(r, off, 0u, C.bad ? qnan : v[0] + d0);
 #pragma unroll
     for (int j = 0; j < N; ++j)
-      A.v_out[(int64_t)(d * n1 + 1 + j) * A.ld + c] = C.bad ? qnan : v[j + 1] + (d0 + u[j]);
+      rsrc_put(r, off, (uint32_t)(1 + j) * row, C.bad ? qnan : v[j + 1] + (d0 + u[j]));
   }
 }
 
@@ -294,31 +336,6 @@ struct LaneInputs : LaneCoefs<N> {
   double v[3][N + 1];
 };
 
-// Raw buffer loads for the one-lane kernels' inputs: one scalar resource per
-// array (base and size), the row as a wave-uniform SGPR offset and the cell
-// as one 32-bit lane offset shared by every load of the cell.  Prefetching a
-// cell's inputs then holds one address register, and the 2N + 1 + D (N + 1)
-// rows cost four resources instead of one per row (a resource per row needed
-// four SGPRs each: 176 at N = 8, which the compiler spilled).  The resource:
-// stride 0 (raw), num_records = the array's bytes (bit pattern, below 2^32:
-// the host checks 8 ((rows - 1) ld + n_cells) < 2^32), and the CDNA word-3
-// flags for 32-bit untyped data; an offset at or past the end reads 0.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const double* base, uint32_t bytes) {
-  constexpr int kRawBufferFlags = 0x00020000;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)bytes,
-                                           kRawBufferFlags);
-}
-
-__device__ __forceinline__ double rsrc_at(__amdgpu_buffer_rsrc_t r, uint32_t lane_off,
-                                          uint32_t row_off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, row_off, 0));
-}
-
-// Bytes of an SoA array of `rows` rows of n_cells cells, leading dimension ld.
-__device__ __forceinline__ uint32_t array_bytes(int64_t rows, const CellArgs& A) {
-  return (uint32_t)(8 * ((rows - 1) * A.ld + A.n_cells));
-}
-
 // Inputs of cell c, given as the byte offset off = 8 c.
 template <int N>
 __device__ __forceinline__ void lane_load(LaneCoefs<N>& X, const CellArgs& A, uint32_t off) {
@@ -340,12 +357,15 @@ __device__ __forceinline__ void lane_load(LaneInputs<N>& X, const CellArgs& A, u
   lane_load<N>(static_cast<LaneCoefs<N>&>(X), A, off);
   const uint32_t row = (uint32_t)(8 * A.ld);
   const int n1 = N + 1;
-  const __amdgpu_buffer_rsrc_t rv = raw_rsrc(A.v_in, array_bytes((int64_t)A.n_dim * n1, A));
+  // one resource per component, so that the row offsets j * row are the
+  // species rows' own (N + 1 scalar offsets in all, not D (N + 1))
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int dd = d < A.n_dim ? d : A.n_dim - 1;
+    const __amdgpu_buffer_rsrc_t rv =
+        raw_rsrc(A.v_in + (int64_t)dd * n1 * A.ld, array_bytes(n1, A));
 #pragma unroll
-    for (int j = 0; j <= N; ++j) X.v[d][j] = rsrc_at(rv, off, (uint32_t)(dd * n1 + j) * row);
+    for (int j = 0; j <= N; ++j) X.v[d][j] = rsrc_at(rv, off, (uint32_t)j * row);
   }
 }
 

@@ -45,6 +45,14 @@ __device__ __forceinline__ double pair_sum(double x, int h) {
   return h == 0 ? x + y : y + x;
 }
 
+template <int H>
+__device__ __forceinline__ void pair_copy(double (&W)[H][2 * H], const double (&Z)[H][2 * H]) {
+#pragma unroll
+  for (int r = 0; r < H; ++r)
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) W[r][k] = Z[r][k];
+}
+
 // kMinWaves: waves per SIMD the register allocation must allow (2 forces
 // N = 7, 8 into 256 registers at the price of a few spills in the squaring
 // loop; 1 lets them use accumulation registers instead).  N = 9, 10 need
@@ -211,7 +219,7 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
         for (int r = 0; r < H; ++r)
 #pragma unroll
           for (int k = 0; k < W2; ++k) {
-            const double wv = Y[r2][k] + (k == r2 ? 2.0 : 0.0);
+            const double wv = k == r2 ? Y[r2][k] + 2.0 : Y[r2][k];
             T[r][k] = fma(dY[r][r2], wv, fma(Y[r][r2], dY[r2][k], T[r][k]));
           }
       }
@@ -221,7 +229,8 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
       for (int r2 = 0; r2 < H; ++r2)
 #pragma unroll
         for (int k = 0; k < W2; ++k) {
-          const double py = pair_swap(Y[r2][(k + H) % W2]) + (k == H + r2 ? 2.0 : 0.0);
+          const double sy = pair_swap(Y[r2][(k + H) % W2]);
+          const double py = k == H + r2 ? sy + 2.0 : sy;
           const double pdy = pair_swap(dY[r2][(k + H) % W2]);
 #pragma unroll
           for (int r = 0; r < H; ++r)
@@ -250,13 +259,14 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
         for (int r = 0; r < H; ++r)
 #pragma unroll
           for (int k = 0; k < W2; ++k)
-            T[r][k] = fma(Y[r][r2], Y[r2][k] + (k == r2 ? 2.0 : 0.0), T[r][k]);
+            T[r][k] = fma(Y[r][r2], k == r2 ? Y[r2][k] + 2.0 : Y[r2][k], T[r][k]);
       }
 #pragma unroll
       for (int r2 = 0; r2 < H; ++r2)
 #pragma unroll
         for (int k = 0; k < W2; ++k) {
-          const double py = pair_swap(Y[r2][(k + H) % W2]) + (k == H + r2 ? 2.0 : 0.0);
+          const double sy = pair_swap(Y[r2][(k + H) % W2]);
+          const double py = k == H + r2 ? sy + 2.0 : sy;
 #pragma unroll
           for (int r = 0; r < H; ++r) T[r][k] = fma(Y[r][H + r2], py, T[r][k]);
         }
@@ -371,6 +381,41 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
   }
 }
 
+// One squaring W = Z (Z + 2I) of the rows of this lane (lane-relative
+// columns; the partner's rows fetched element by element by DPP, one swap per
+// dword, used for all H own rows).  With go false, W = Z.
+template <int H>
+__device__ __forceinline__ void pair_square_step(bool go, const double (&Z)[H][2 * H],
+                                                 double (&W)[H][2 * H]) {
+  constexpr int W2 = 2 * H;
+  if (!go) {
+    pair_copy<H>(W, Z);
+    return;
+  }
+  // own rows of the right factor: relative column l of my rows is my row l
+  // (the chains start with a product rather than an FMA into zero)
+#pragma unroll
+  for (int l = 0; l < H; ++l) {
+#pragma unroll
+    for (int k = 0; k < W2; ++k) {
+      const double b = k == l ? Z[l][k] + 2.0 : Z[l][k];
+#pragma unroll
+      for (int r = 0; r < H; ++r) W[r][k] = l == 0 ? Z[r][l] * b : fma(Z[r][l], b, W[r][k]);
+    }
+  }
+  // the partner's rows: its row l is my relative column H + l
+#pragma unroll
+  for (int l = 0; l < H; ++l) {
+#pragma unroll
+    for (int k = 0; k < W2; ++k) {
+      const double sz = pair_swap(Z[l][(k + H) % W2]);
+      const double b = k == H + l ? sz + 2.0 : sz;
+#pragma unroll
+      for (int r = 0; r < H; ++r) W[r][k] = fma(Z[r][H + l], b, W[r][k]);
+    }
+  }
+}
+
 // The forward with two lanes per cell, for the species counts where one lane
 // cannot hold Z and the squaring's product buffer (2 N^2 doubles) and the
 // 16 x 16 MFMA tile is mostly padding (N = 9, 10; valid for any N <= 10).
@@ -458,40 +503,18 @@ __device__ __forceinline__ void pair_forward_cell(const CellArgs& A, int64_t c, 
     }
   }
 
-  // squarings Z <- Z (Z + 2I); the partner's rows by DPP, columns half-rotated
+  // squarings Z <- Z (Z + 2I), two per trip between Z and T so that no copy
+  // is needed while every lane of the wavefront is still squaring
   const int s_max = wave_max_int(s);
-  for (int it = 0; it < s_max; ++it) {
-    double T[H][W2];
-#pragma unroll
-    for (int r = 0; r < H; ++r)
-#pragma unroll
-      for (int k = 0; k < W2; ++k) T[r][k] = 0.0;
-    // own rows of the right factor: relative column l of my rows is my row l
-#pragma unroll
-    for (int l = 0; l < H; ++l) {
-#pragma unroll
-      for (int k = 0; k < W2; ++k) {
-        const double b = Z[l][k] + ((k == l) ? 2.0 : 0.0);
-#pragma unroll
-        for (int r = 0; r < H; ++r) T[r][k] = fma(Z[r][l], b, T[r][k]);
-      }
-    }
-    // the partner's rows: its row l is my relative column H + l
-#pragma unroll
-    for (int l = 0; l < H; ++l) {
-#pragma unroll
-      for (int k = 0; k < W2; ++k) {
-        const double b = pair_swap(Z[l][(k + H) % W2]) + ((k == H + l) ? 2.0 : 0.0);
-#pragma unroll
-        for (int r = 0; r < H; ++r) T[r][k] = fma(Z[r][H + l], b, T[r][k]);
-      }
-    }
-    if (it < s) {
-#pragma unroll
-      for (int r = 0; r < H; ++r)
-#pragma unroll
-        for (int k = 0; k < W2; ++k) Z[r][k] = T[r][k];
-    }
+  double T[H][W2];
+  int it = 0;
+  for (; it + 2 <= s_max; it += 2) {
+    pair_square_step<H>(it < s, Z, T);
+    pair_square_step<H>(it + 1 < s, T, Z);
+  }
+  if (it < s) {
+    pair_square_step<H>(true, Z, T);
+    pair_copy<H>(Z, T);
   }
 
   // apply: u = Z dv for the own rows, e.u summed over the pair

@@ -41,9 +41,11 @@ __device__ __forceinline__ void stage_tile(double* buf, int g, int j, const v4d&
   __builtin_amdgcn_wave_barrier();
 }
 
+// The A operand of the first KT steps (columns 0 .. 4 KT - 1 of the tile).
+template <int KT = 4>
 __device__ __forceinline__ void load_a_ops(const double* buf, int g, int i, double (&A)[4]) {
 #pragma unroll
-  for (int t = 0; t < 4; ++t) A[t] = buf[i * kLdsStride + 4 * t + g];
+  for (int t = 0; t < 4; ++t) A[t] = t < KT ? buf[i * kLdsStride + 4 * t + g] : 0.0;
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -53,6 +55,21 @@ __device__ __forceinline__ v4d mma16(const double (&A)[4], const double (&B)[4],
   for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], B[t], acc, 0, 0, 0);
   return acc;
 }
+
+// D = A B + C over k = 4 KT.  When the contraction runs over the species of
+// an N x N block zero-padded to the tile (rows N .. 15 of B zero), the steps
+// t >= ceil(N / 4) add exact zeros, so KT = ceil(N / 4) gives the same
+// values as k = 16 with 4 - KT fewer MFMAs.
+template <int KT>
+__device__ __forceinline__ v4d mma_k(const double (&A)[4], const double (&B)[4], v4d acc) {
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[t], B[t], acc, 0, 0, 0);
+  return acc;
+}
+
+// MFMA steps of an N-species contraction (N = 0: not known at compile time).
+constexpr int mfma_steps(int N) { return N > 0 ? (N + 3) / 4 : 4; }
 
 // ---- the forward update: four cells per wavefront ---------------------------
 //
@@ -191,7 +208,7 @@ __device__ __forceinline__ double norm1_tile(const v4d& X) {
   return row_max(sum_rows(part));
 }
 
-template <int Q, bool BT = false>
+template <int Q, bool BT = false, int KT = 4>
 __device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const double (&rm)[4],
                                          int m, int r, double* stage, int g, int j) {
   v4d P[Q + 1];
@@ -216,8 +233,8 @@ __device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const 
     for (int k = r - 2; k >= 0; --k) {
       double Af[4];
       stage_tile(stage, g, j, F);
-      load_a_ops(stage, g, j, Af);
-      F = mma16(Af, Bq, bbar(k));
+      load_a_ops<KT>(stage, g, j, Af);
+      F = mma_k<KT>(Af, Bq, bbar(k));
     }
     return F;
   } else {
@@ -258,8 +275,8 @@ __device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const 
     } else {
       double Af[4];
       stage_tile(stage, g, j, F);
-      load_a_ops(stage, g, j, Af);
-      F = mma16(Af, Bq, bbar(k));
+      load_a_ops<KT>(stage, g, j, Af);
+      F = mma_k<KT>(Af, Bq, bbar(k));
     }
   }
   return F;
@@ -273,6 +290,7 @@ __device__ __forceinline__ v4d quad_poly(const v4d& M, const QuadRows& R, const 
 // read back as the A operand, Z itself is the B operand and the accumulator
 // starts at zero.  The extra rounding of the diagonal entries 2 + Z_jj is
 // of the same size as that of the sum 2 Z + Z Z.
+template <int KT = 4>
 __device__ __forceinline__ v4d square_step(const v4d& Z, double* stage, int g, int j,
                                            int diag_slot) {
   double Az[4], Bz[4];
@@ -281,8 +299,8 @@ __device__ __forceinline__ v4d square_step(const v4d& Z, double* stage, int g, i
   stage_tile(stage, g, j, Z);
   if (g == 0) atomicAdd(stage + diag_slot, 2.0);
   __builtin_amdgcn_wave_barrier();
-  load_a_ops(stage, g, j, Az);
-  return mma16(Az, Bz, v4d{0.0, 0.0, 0.0, 0.0});
+  load_a_ops<KT>(stage, g, j, Az);
+  return mma_k<KT>(Az, Bz, v4d{0.0, 0.0, 0.0, 0.0});
 }
 
 // The forward update of cells c0 .. c0+3 (those below n_cells) by one
@@ -354,7 +372,9 @@ __device__ __forceinline__ QuadCell quad_setup(const double* rho_g, const double
 // workgroup to store (group_store).
 // METHOD: the scaling step (kStageTaylor, kStageTaylorBound: with the
 // second modification, kStagePade: the diagonal Pade approximant).
-template <int METHOD = kStageTaylor>
+// KT: MFMA steps per product, mfma_steps(N) where N is a compile-time
+// constant of the caller, else 4.
+template <int METHOD = kStageTaylor, int KT = 4>
 __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N, int64_t c0,
                                                   int lane, double* lds, bool store = true) {
   const int g = lane >> 4, j = lane & 15;
@@ -463,10 +483,10 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
       Z = pade_stage(M, R, rm, kk, N, stage, g, j);
     } else {
       switch (q) {  // uniform; one code path per power count
-        case 2: Z = quad_poly<2, BT>(M, R, rm, m, r, stage, g, j); break;
-        case 3: Z = quad_poly<3, BT>(M, R, rm, m, r, stage, g, j); break;
-        case 4: Z = quad_poly<4, BT>(M, R, rm, m, r, stage, g, j); break;
-        default: Z = quad_poly<5, BT>(M, R, rm, m, r, stage, g, j); break;
+        case 2: Z = quad_poly<2, BT, KT>(M, R, rm, m, r, stage, g, j); break;
+        case 3: Z = quad_poly<3, BT, KT>(M, R, rm, m, r, stage, g, j); break;
+        case 4: Z = quad_poly<4, BT, KT>(M, R, rm, m, r, stage, g, j); break;
+        default: Z = quad_poly<5, BT, KT>(M, R, rm, m, r, stage, g, j); break;
       }
     }
 
@@ -474,10 +494,10 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
     // the operand registers alternate
     int it = 0;
     for (; it + 2 <= s; it += 2) {
-      const v4d Z1 = square_step(Z, stage, g, j, diag_slot);
-      Z = square_step(Z1, stage, g, j, diag_slot);
+      const v4d Z1 = square_step<KT>(Z, stage, g, j, diag_slot);
+      Z = square_step<KT>(Z1, stage, g, j, diag_slot);
     }
-    if (it < s) Z = square_step(Z, stage, g, j, diag_slot);
+    if (it < s) Z = square_step<KT>(Z, stage, g, j, diag_slot);
 
     // u = Z dv for every component at once (B operand: lane (g, j < D) holds
     // the relative velocities of rows 4 t + g, component j)
@@ -487,8 +507,8 @@ __device__ __forceinline__ void wave_forward_quad(const CellArgs& A, const int N
     for (int t = 0; t < 4; ++t) Bd[t] = (j < D && 4 * t + g < N) ? x[t] - v0 : 0.0;
     double Az[4];
     stage_tile(stage, g, j, Z);
-    load_a_ops(stage, g, j, Az);
-    const v4d U = mma16(Az, Bd, v4d{0.0, 0.0, 0.0, 0.0});
+    load_a_ops<KT>(stage, g, j, Az);
+    const v4d U = mma_k<KT>(Az, Bd, v4d{0.0, 0.0, 0.0, 0.0});
     double eu = 0.0;
     const double* re = qe + 16 * c + 4 * g;  // e of rows 4 v + g
 #pragma unroll
@@ -540,7 +560,8 @@ __global__ void __launch_bounds__(256, METHOD == kStageTaylor ? 5 : 4)
   const int64_t g0 = logical * 16;  // the workgroup's first cell
   if (g0 >= A.n_cells) return;     // uniform over the workgroup
   const int64_t c0 = g0 + 4 * w;
-  if (c0 < A.n_cells) wave_forward_quad<METHOD>(A, N, c0, lane, lds + w * kQuadDoubles, false);
+  if (c0 < A.n_cells)
+    wave_forward_quad<METHOD, mfma_steps(N)>(A, N, c0, lane, lds + w * kQuadDoubles, false);
   __syncthreads();
   group_store(A, N, g0, lds);
 }
