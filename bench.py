@@ -190,6 +190,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times), the "
                          "reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--side-only", action="store_true",
+                    help="only the side measurements of the default run (fused adjoint, "
+                         "batched, RK1, bound test, Pade), one JSON object; the default run "
+                         "takes them from a child process started this way")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -233,6 +237,9 @@ def main():
         return
     if args.batched:
         print(json.dumps(batched_only(torch, ops, workloads, dev, args)), flush=True)
+        return
+    if args.side_only:
+        print(json.dumps(side_measurements(torch, ops, _lib, workloads, dev)), flush=True)
         return
     if args.rk1:
         print(json.dumps(rk1_only(torch, ops, workloads, dev, name, args)), flush=True)
@@ -305,25 +312,63 @@ def main():
         "roofline": roof,
         "wall_s_timed": wall,
     }
-    # the side measurements each report an error in place rather than lose
-    # the line (the headline above is complete by now)
-    def side(key, fn):
+    # The side measurements run in a child process (this script with
+    # --side-only), so that the headline line above survives whatever happens
+    # to them; each reports an error in place instead.
+    if not args.no_comparisons:
+        res.update(_side_in_child())
+    if args.extra:
         try:
-            res[key] = fn()
+            res["extra"] = extra_measurements(torch, ops, workloads, dev)
+        except Exception as e:  # noqa: BLE001
+            res["extra"] = {"error": f"{type(e).__name__}: {e}"}
+    if not args.no_cpu_baseline:
+        try:
+            res["cpu_baseline"] = cpu_baseline(d)
+        except Exception as e:  # noqa: BLE001
+            res["cpu_baseline"] = {"error": f"{type(e).__name__}: {e}"}
+    print(json.dumps(res), flush=True)
+
+
+SIDE_KEYS = ("fwd_bwd_vs_fwd", "batched_vs_plain", "rk1_vs_expm", "bound_test", "pade_vs_taylor")
+
+
+def side_measurements(torch, ops, _lib, workloads, dev):
+    """The comparisons beside the headline, each reporting an error in place."""
+    res = {}
+    fns = {"fwd_bwd_vs_fwd": lambda: adjoint_measurement(torch, ops, workloads, dev),
+           "batched_vs_plain": lambda: batched_measurement(torch, ops, workloads, dev),
+           "rk1_vs_expm": lambda: rk1_measurement(torch, ops, workloads, dev),
+           "bound_test": lambda: bound_test_measurement(torch, ops, _lib, workloads, dev),
+           "pade_vs_taylor": lambda: pade_measurement(torch, ops, _lib, workloads, dev)}
+    for key in SIDE_KEYS:
+        _progress(f"side measurement: {key}")
+        try:
+            res[key] = fns[key]()
         except Exception as e:  # noqa: BLE001
             res[key] = {"error": f"{type(e).__name__}: {e}"}
+    return res
 
-    if not args.no_comparisons:
-        side("fwd_bwd_vs_fwd", lambda: adjoint_measurement(torch, ops, workloads, dev))
-        side("batched_vs_plain", lambda: batched_measurement(torch, ops, workloads, dev))
-        side("rk1_vs_expm", lambda: rk1_measurement(torch, ops, workloads, dev))
-        side("bound_test", lambda: bound_test_measurement(torch, ops, _lib, workloads, dev))
-        side("pade_vs_taylor", lambda: pade_measurement(torch, ops, _lib, workloads, dev))
-    if args.extra:
-        side("extra", lambda: extra_measurements(torch, ops, workloads, dev))
-    if not args.no_cpu_baseline:
-        side("cpu_baseline", lambda: cpu_baseline(d))
-    print(json.dumps(res), flush=True)
+
+def _side_in_child(timeout_s=900):
+    """Run side_measurements in a child process and return its result, or an
+    error entry per key when the child fails (its stderr goes to ours)."""
+    import subprocess
+    try:
+        p = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--side-only"],
+                           stdout=subprocess.PIPE, timeout=timeout_s, check=False, text=True)
+        lines = [ln for ln in p.stdout.splitlines() if ln.strip()]
+        if p.returncode == 0 and lines:
+            return json.loads(lines[-1])
+        why = f"side measurements exited with status {p.returncode}"
+    except subprocess.TimeoutExpired:
+        why = f"side measurements exceeded {timeout_s} s"
+    return {k: {"error": why} for k in SIDE_KEYS}
+
+
+def _progress(msg):
+    """One progress line on stderr (the JSON result goes to stdout)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
 
 
 def _time(torch, fn, steps, warmup, chunks=1):
@@ -451,6 +496,7 @@ def config_report(torch, ops, _lib, workloads, dev):
     out = {"threads": threads}
     for cfg, name, sample in ((1, "n1_closed_form", 4096), (2, "n4_3d", 1 << 16),
                               (3, "n16_stiff_3d", 1 << 13), (5, "n8_adjoint_3d", 1 << 15)):
+        _progress(f"report: config {cfg} ({name})")
         d = workloads.make(name)
         C, N, D = d["rho_g"].shape[0], d["rho_d"].shape[0], d["v"].shape[0]
         T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
@@ -461,7 +507,9 @@ def config_report(torch, ops, _lib, workloads, dev):
         _, _, _, kk, mm, ss = ops.build(T["rho_g"], T["rho_d"], T["t_stop"], d["dt"])
         kk, mm, ss = (x.cpu().numpy() for x in (kk, mm, ss))
         f_alg = float(algorithmic_flops(kk, mm, ss, N, D).sum())
+        _progress(f"report: config {cfg} oracle")
         ref, nrm, r1, rp = _oracle_rates(d, min(sample, C), threads)
+        _progress(f"report: config {cfg} errors")
         row = {"workload": name, "cells": C, "ms": ms, "cells_per_s": C / (ms * 1e-3),
                "fp64_frac": f_alg / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                "hbm_frac": algorithmic_bytes(C, N, D) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -490,11 +538,13 @@ def config_report(torch, ops, _lib, workloads, dev):
             row["fwd_bwd_over_fwd"] = tb / tf
         out[f"config{cfg}"] = row
     # config 4: the batched launch; the oracle on the first 32 blocks
+    _progress("report: config 4 (batched)")
     batch = workloads.make_batched()
     plan = ops.BatchPlan(batch["n_species"], batch["block_cells"], 3, batch["dt"])
     fields, v = plan.pack(batch["blocks"], dev)
     vo = torch.empty_like(v)
     plan.autotune(fields, v, vo)
+    _progress("report: config 4 timing")
     ms = _time(torch, lambda: plan.apply(fields, v, vo), 20, 3)
     cells = len(batch["blocks"]) * batch["block_cells"]
     # algorithmic work: the blocks of each N concatenated, (k*, m*, s*) from drag_build
@@ -507,6 +557,7 @@ def config_report(torch, ops, _lib, workloads, dev):
         kk, mm, ss = _lib_select_cells(ops, cat, batch["dt"], dev)
         f_alg += float(algorithmic_flops(kk, mm, ss, N, 3).sum())
     # the oracle on the first 32 blocks: one thread, then one block per thread
+    _progress("report: config 4 oracle")
     import oracle
     from concurrent.futures import ThreadPoolExecutor
     sample = batch["blocks"][:32]
@@ -533,6 +584,7 @@ def config_report(torch, ops, _lib, workloads, dev):
     exact["note"] = "max over the 32 blocks of each block's max and p99.9"
     exact["max_gpu_vs_oracle_minus_oracle_vs_exact"] = max(
         x["max_gpu_vs_oracle_minus_oracle_vs_exact"] for x in ex)
+    _progress("report: config 4 done")
     plan.close()
     out["config4"] = {"workload": "batched 4096 x 512, N_b ~ U{1..16}", "cells": cells, "ms": ms,
                       "cells_per_s": cells / (ms * 1e-3),

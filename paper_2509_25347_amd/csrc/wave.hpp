@@ -5,8 +5,8 @@
 // lane.hpp) is held as one 16 x 16 tile, zero-padded when N < 16: the
 // species block of the drag problem is exactly the MFMA tile for N = 16.
 // Dense products of the method (Horner steps of the Paterson-Stockmeyer
-// evaluation, the s squarings, the apply) are chains of four 16x16x4 FP64
-// MFMAs (k = 16).
+// evaluation, the s squarings, the apply) are chains of 16x16x4 FP64 MFMAs:
+// four (k = 16), or ceil(N / 4) where the kernel is compiled for N.
 //
 // Register layouts of v_mfma_f64_16x16x4 (lane l = 16 g + j, g = l / 16):
 //   A operand (16 x 4, step t):  A[i = j][4t + g]
