@@ -794,9 +794,9 @@ def rk1_measurement(torch, ops, workloads, dev, names=("n16_stiff_3d", "n8_adjoi
         T = {k: torch.from_numpy(d[k]).to(dev) for k in ("rho_g", "rho_d", "t_stop", "v")}
         o1, o2 = torch.empty_like(T["v"]), torch.empty_like(T["v"])
         t_rk1 = _time(torch, lambda: ops.rk1_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
-                                                   d["dt"], out=o1), 30, 3)
+                                                   d["dt"], out=o1), 30, 3, chunks=5)
         t_exp = _time(torch, lambda: ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"],
-                                                    d["dt"], out=o2), 20, 3)
+                                                    d["dt"], out=o2), 20, 3, chunks=5)
         scale = T["v"].abs().amax(dim=1)
         gap = ((o1 - o2).abs().amax(dim=1) / scale).amax(dim=0)
         res[name] = {"n_cells": C, "n_species": N, "rk1_ms": t_rk1, "expm_ms": t_exp,
