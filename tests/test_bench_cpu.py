@@ -83,3 +83,15 @@ def test_profile_summaries_match_the_sources(name, kernel, workload, fields):
     assert fields["source_sha256"] == bench.source_hash(kernel), name
     assert float(fields["hbm_bytes_per_launch"]) > 0
     assert bench.profiled_traffic(kernel, workload) == float(fields["hbm_bytes_per_launch"])
+
+
+def test_side_measurements_fail_in_place():
+    """A child that cannot measure (here: no GPU) costs only the side keys,
+    each an error entry, never the caller's line."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("the failure path needs a process without a GPU")
+    res = bench._side_in_child(timeout_s=300)
+    assert set(res) == set(bench.SIDE_KEYS)
+    for key in bench.SIDE_KEYS:
+        assert "error" in res[key], key
