@@ -233,9 +233,8 @@ int drag_expm_apply_backward(const drag_desc *desc, const double *rho_g,
  *     v [D][N_b + 1][block_cells].
  * The plan (created once, on the host and the current device) holds the
  * device block table, the launch configuration chosen per N by the
- * autotuner, and an instantiated hipGraph of the whole update: the one-lane
- * grids, the two-lane grids and the MFMA launches as three concurrent
- * branches.
+ * autotuner, and an instantiated hipGraph of the whole update: the lane
+ * grids and the MFMA launches as two concurrent branches.
  */
 typedef struct drag_plan drag_plan;
 

@@ -514,8 +514,8 @@ struct drag_plan {
   int64_t* d_field_off = nullptr;
   int64_t* d_v_off = nullptr;
   unsigned int* d_counter = nullptr;
-  hipStream_t cap_stream = nullptr, side_stream = nullptr, pair_stream = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join_pair = nullptr;
+  hipStream_t cap_stream = nullptr, side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const double* g_fields = nullptr;
@@ -542,10 +542,8 @@ static void plan_free(drag_plan* P) {
   plan_drop_graph(P);
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
-  if (P->ev_join_pair) (void)hipEventDestroy(P->ev_join_pair);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
-  if (P->pair_stream) (void)hipStreamDestroy(P->pair_stream);
   for (BatchVariant& V : P->var) {
     if (V.d_wave) (void)hipFree(V.d_wave);
     if (V.d_wave_blocks) (void)hipFree(V.d_wave_blocks);
@@ -644,50 +642,33 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
     return DRAG_ERR_HIP;
   if (hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking) != hipSuccess)
     return DRAG_ERR_HIP;
-  if (hipStreamCreateWithFlags(&P->pair_stream, hipStreamNonBlocking) != hipSuccess)
-    return DRAG_ERR_HIP;
   if (hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess)
     return DRAG_ERR_HIP;
   if (hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess)
     return DRAG_ERR_HIP;
-  if (hipEventCreateWithFlags(&P->ev_join_pair, hipEventDisableTiming) != hipSuccess)
-    return DRAG_ERR_HIP;
   return DRAG_OK;
 }
 
-// Enqueue one batched update (variant lmax) on `main`, the one-lane grids on
-// `side` and the two-lane grids on `pair` between a fork and a join:
-// captured, this is the plan's graph.
+// Enqueue one batched update (variant lmax) on `main`, the lane grids on
+// `side` between a fork and a join: captured, this is the plan's graph.
 static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
-                        const double* v_in, double* v_out, hipStream_t main, hipStream_t side,
-                        hipStream_t pair) {
+                        const double* v_in, double* v_out, hipStream_t main, hipStream_t side) {
   int v = 0;
   while (v + 1 < kBatchVariants && kBatchLmax[v] != lmax) ++v;
   const BatchVariant& V = P->var[v];
   BatchArgs B{nullptr, P->d_field_off, P->d_v_off, fields, v_in, v_out, P->d_counter,
               0,       P->block_cells, P->n_dim, P->option, P->dt, {}};
   for (int n = 0; n <= kMaxSpecies; ++n) B.k_max_n[n] = P->k_n[n];
-  bool any_pair = false;
-  for (int n = kLaneMaxN + 1; n <= kPairMaxN; ++n) any_pair = any_pair || V.n_lane[n] > 0;
   if (hipEventRecord(P->ev_fork, main) != hipSuccess) return DRAG_ERR_HIP;
   if (hipStreamWaitEvent(side, P->ev_fork, 0) != hipSuccess) return DRAG_ERR_HIP;
-  if (any_pair && hipStreamWaitEvent(pair, P->ev_fork, 0) != hipSuccess) return DRAG_ERR_HIP;
-  for (int n = 1; n <= kLaneMaxN; ++n) {
+  for (int n = 1; n <= kPairMaxN; ++n) {
     if (V.n_lane[n] == 0) continue;
     BatchArgs L = B;
     L.items = V.d_lane[n];
     L.n_items = V.n_lane[n];
     batched_lane(n, L, side);
   }
-  for (int n = kPairMaxN; n > kLaneMaxN; --n) {  // largest N first, as the MFMA branch
-    if (V.n_lane[n] == 0) continue;
-    BatchArgs L = B;
-    L.items = V.d_lane[n];
-    L.n_items = V.n_lane[n];
-    batched_lane(n, L, pair);
-  }
   if (hipEventRecord(P->ev_join, side) != hipSuccess) return DRAG_ERR_HIP;
-  if (any_pair && hipEventRecord(P->ev_join_pair, pair) != hipSuccess) return DRAG_ERR_HIP;
   if (V.n_wave > 0 && mode == kWavePersistent) {
     BatchArgs W = B;
     W.items = V.d_wave;
@@ -713,8 +694,6 @@ static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
     }
   }
   if (hipStreamWaitEvent(main, P->ev_join, 0) != hipSuccess) return DRAG_ERR_HIP;
-  if (any_pair && hipStreamWaitEvent(main, P->ev_join_pair, 0) != hipSuccess)
-    return DRAG_ERR_HIP;
   return hip_status(hipGetLastError());
 }
 
@@ -725,8 +704,7 @@ static int plan_capture(drag_plan* P, int lmax, int mode, const double* fields,
   if (hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return DRAG_ERR_HIP;
   const int rc =
-      plan_enqueue(P, lmax, mode, fields, v_in, v_out, P->cap_stream, P->side_stream,
-                   P->pair_stream);
+      plan_enqueue(P, lmax, mode, fields, v_in, v_out, P->cap_stream, P->side_stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
   if (rc || e != hipSuccess) {
@@ -1145,9 +1123,7 @@ int drag_plan_autotune(drag_plan* P, const double* fields, const double* v_in, d
       if (!rc) P->k_n[n] = kbest;
     }
     // leave v_out holding the result of the chosen configuration
-    if (!rc)
-      rc = plan_enqueue(P, P->lmax, P->wave_mode, fields, v_in, v_out, st, P->side_stream,
-                        P->pair_stream);
+    if (!rc) rc = plan_enqueue(P, P->lmax, P->wave_mode, fields, v_in, v_out, st, P->side_stream);
     if (!rc) rc = hip_status(hipStreamSynchronize(st));
   }
   (void)hipEventDestroy(e0);
