@@ -50,7 +50,11 @@ def _static_call(_lib, batch, bc, D, k_max, fields, v_in, v_out):
 def test_static_batched_matches_the_plan_twice(dev):
     from paper_2509_25347_amd import _lib, ops
     cases = [(W.make_batched(n_blocks=300, block_cells=100, D=3, seed_cfg=61), 100, 3, 9),
-             (W.make_batched(n_blocks=37, block_cells=70, D=2, seed_cfg=62), 70, 2, _lib.K_AUTO)]
+             (W.make_batched(n_blocks=37, block_cells=70, D=2, seed_cfg=62), 70, 2, _lib.K_AUTO),
+             # one-cell blocks (every item a one-lane tail), D = 1
+             (W.make_batched(n_blocks=50, block_cells=1, D=1, seed_cfg=63), 1, 1, 9),
+             # one-lane blocks only (no MFMA grid, no two-lane grid), ragged items
+             (W.make_batched(n_blocks=40, block_cells=129, D=3, n_max=8, seed_cfg=64), 129, 3, 9)]
     for k, (batch, bc, D, K) in enumerate(cases):
         print(f"static batched call {k}: {len(batch['blocks'])} blocks x {bc} cells, D={D}",
               flush=True)
