@@ -649,8 +649,9 @@ static int plan_init(drag_plan* P, const drag_batch_desc* bd) {
   return DRAG_OK;
 }
 
-// Enqueue one batched update (variant lmax) on `main`, the lane grids on
-// `side` between a fork and a join: captured, this is the plan's graph.
+// Enqueue one batched update (variant lmax): the MFMA grids on `main`, the
+// lane grids on `side` between a fork and a join (the largest two-lane grid
+// after the MFMA grids on `main`): captured, this is the plan's graph.
 static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
                         const double* v_in, double* v_out, hipStream_t main, hipStream_t side) {
   int v = 0;
@@ -661,8 +662,11 @@ static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
   for (int n = 0; n <= kMaxSpecies; ++n) B.k_max_n[n] = P->k_n[n];
   if (hipEventRecord(P->ev_fork, main) != hipSuccess) return DRAG_ERR_HIP;
   if (hipStreamWaitEvent(side, P->ev_fork, 0) != hipSuccess) return DRAG_ERR_HIP;
+  // The largest two-lane grid (N = lmax) goes to the end of the MFMA branch:
+  // behind the one-lane grids it ran alone after the MFMA grids had ended.
+  const int tail_n = lmax > kLaneMaxN ? lmax : 0;
   for (int n = 1; n <= kPairMaxN; ++n) {
-    if (V.n_lane[n] == 0) continue;
+    if (V.n_lane[n] == 0 || n == tail_n) continue;
     BatchArgs L = B;
     L.items = V.d_lane[n];
     L.n_items = V.n_lane[n];
@@ -692,6 +696,12 @@ static int plan_enqueue(drag_plan* P, int lmax, int mode, const double* fields,
       W.n_items = V.n_wave_n[n];
       batched_wave_n(n, W, gpb, main, mode == kWavePerNPade);
     }
+  }
+  if (tail_n && V.n_lane[tail_n] > 0) {
+    BatchArgs L = B;
+    L.items = V.d_lane[tail_n];
+    L.n_items = V.n_lane[tail_n];
+    batched_lane(tail_n, L, main);
   }
   if (hipStreamWaitEvent(main, P->ev_join, 0) != hipSuccess) return DRAG_ERR_HIP;
   return hip_status(hipGetLastError());
