@@ -350,7 +350,7 @@ def side_measurements(torch, ops, _lib, workloads, dev):
     return res
 
 
-def _side_in_child(timeout_s=900):
+def _side_in_child(timeout_s=300):
     """Run side_measurements in a child process and return its result, or an
     error entry per key when the child fails (its stderr goes to ours)."""
     import subprocess
