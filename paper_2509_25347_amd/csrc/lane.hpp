@@ -96,6 +96,13 @@ __device__ __forceinline__ int wave_max_int(int x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
+// Smallest x over the wavefront, wave-uniform like wave_max_int.
+__device__ __forceinline__ int wave_min_int(int x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = min(x, __shfl_xor(x, off, 64));
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
 // Per-cell set-up: coefficients, ||A||_1 (bit-exact order), Alg. 1.
 template <int N>
 struct LaneCell {
@@ -186,12 +193,20 @@ __device__ __forceinline__ void lane_expm(double (&Z)[N][N], const LaneCell<N>& 
   }
   const int m_max = wave_max_int(C.kms.m);
   lane_taylor<N>(Z, b, pb, C.kms.m, m_max);
-  // squarings to the wavefront's largest s, each lane under its own s; two
-  // per trip between Z and T so that no copy is needed on the common path
+  // squarings to the wavefront's largest s, each lane under its own s, two
+  // per trip between Z and T.  Up to the wavefront's smallest s every lane
+  // squares, with no branch; past it the lanes that are done copy, and the
+  // product that may or may not be taken is formed in temporaries and moved
+  // (N^2 moves per squaring, 12-25 % of the squaring's instructions).
   const int s = C.kms.s;
   const int s_max = wave_max_int(s);
+  const int s_min = wave_min_int(s);
   double T[N][N];
   int it = 0;
+  for (; it + 2 <= s_min; it += 2) {
+    lane_square_to<N>(T, Z);
+    lane_square_to<N>(Z, T);
+  }
   for (; it + 2 <= s_max; it += 2) {
     if (it < s) lane_square_to<N>(T, Z);
     else lane_copy<N>(T, Z);

@@ -499,15 +499,24 @@ __device__ __forceinline__ void pair_forward_cell(const CellArgs& A, int64_t c, 
 #pragma unroll
       for (int k = 0; k < W2; ++k) rs += Z[r][k];
 #pragma unroll
-      for (int k = 0; k < W2; ++k) Z[r][k] = fma(Z[r][k], nb[k], rs * npb[k]);
+      for (int k = 0; k < W2; ++k) Z[r][k] = fma(rs, npb[k], Z[r][k] * nb[k]);
     }
   }
 
-  // squarings Z <- Z (Z + 2I), two per trip between Z and T so that no copy
-  // is needed while every lane of the wavefront is still squaring
+  // squarings Z <- Z (Z + 2I), two per trip between Z and T.  Each lane
+  // squares under its own s (the product that may or may not be taken is
+  // formed in temporaries and moved: H W2 moves per squaring); for H <= 5 a
+  // branch-free loop runs first, up to the wavefront's smallest s.  At H = 6
+  // the branch-free loop was allocated worse than the branching one (more
+  // moves and accumulation-register traffic; 5 % slower at N = 12).
   const int s_max = wave_max_int(s);
+  const int s_min = H <= 5 ? wave_min_int(s) : 0;
   double T[H][W2];
   int it = 0;
+  for (; it + 2 <= s_min; it += 2) {
+    pair_square_step<H>(true, Z, T);
+    pair_square_step<H>(true, T, Z);
+  }
   for (; it + 2 <= s_max; it += 2) {
     pair_square_step<H>(it < s, Z, T);
     pair_square_step<H>(it + 1 < s, T, Z);
