@@ -388,6 +388,34 @@ def test_pair_forward_edges(ops, dev, orc, N):
     assert np.array_equal(np.isnan(got), np.isnan(ref))
 
 
+@pytest.mark.parametrize("N", [2, 4, 5, 7, 8, 9, 10, 11, 12])
+def test_squarings_wave_uniform_and_mixed_s(ops, dev, orc, N):
+    """The vector-ALU forwards square without a per-lane branch up to the
+    wavefront's smallest s*, then under it: one cell repeated over whole
+    wavefronts (every lane the same s*, odd and even: doubling dt adds one
+    squaring), and mild cells (s* = 0) interleaved with stiff ones."""
+    from paper_2509_25347_amd import _lib
+    assert _lib.get_mapping(N) == _lib.MAP_LANE
+    base = W.make_stiff(N, 8)
+    C = 300
+    rep = {k: np.ascontiguousarray(np.repeat(base[k][..., 3:4], C, axis=-1))
+           for k in ("rho_g", "rho_d", "t_stop", "v")}
+    seen = set()
+    for j in range(3):
+        d = dict(rep, dt=base["dt"] * 2.0 ** j)
+        ref, kms, nrm, st = orc.apply_cells(d["rho_g"], d["rho_d"], d["t_stop"], d["v"], d["dt"])
+        seen.add(int(kms[2][0]) % 2)
+        assert len(set(kms[2].tolist())) == 1
+        assert_parity(orc, run(ops, d, dev), ref, d, f"N={N} uniform s, dt*2^{j}")
+    assert seen == {0, 1}
+    mix = W.make_stiff(N, C)
+    mix["t_stop"][:, ::2] = 1e8  # ||dt K||_1 tiny: s* = 0 on every other cell
+    ref, kms, nrm, st = orc.apply_cells(mix["rho_g"], mix["rho_d"], mix["t_stop"], mix["v"],
+                                        mix["dt"])
+    assert int(kms[2][::2].max()) == 0 and int(kms[2][1::2].min()) > 0
+    assert_parity(orc, run(ops, mix, dev), ref, mix, f"N={N} s* = 0 beside stiff cells")
+
+
 def test_wave_bad_cells_inside_quads(ops, dev, orc):
     """Bad cells next to good ones in the same quad of the N = 16 kernel."""
     d = W.make("n16_stiff_3d", 64)
