@@ -418,7 +418,7 @@ __device__ __forceinline__ void pair_square_step(bool go, const double (&Z)[H][2
 
 // The forward with two lanes per cell, for the species counts where one lane
 // cannot hold Z and the squaring's product buffer (2 N^2 doubles) and the
-// 16 x 16 MFMA tile is mostly padding (N = 9, 10; valid for any N <= 10).
+// 16 x 16 MFMA tile is mostly padding (N = 9..12).
 // Same layout as the adjoint above: lane h holds rows h H .. h H + H - 1 in
 // the lane-relative column order.  Horner in the structured matrix,
 // F <- (F + c I) M with (F M)_ik = -F_ik b_k - (sum_l F_il) pb_k, is
@@ -563,9 +563,10 @@ __device__ __forceinline__ void pair_forward_cell(const CellArgs& A, int64_t c, 
 }
 
 // Waves per SIMD the forward's register allocation must allow: 2 up to
-// N = 10 (a few VGPRs spill, and the second wavefront hides the latencies:
-// 1.27-1.36x faster than 1 wave with accumulation registers), 1 above
-// (Z and the product buffer alone fill 256 registers).
+// N = 10 (nothing spills, the squarings alternating between Z and T, and
+// the second wavefront hides the latencies: 1.27-1.36x faster than 1 wave
+// with accumulation registers), 1 above (Z and the product buffer alone
+// fill 256 registers).
 template <int N>
 constexpr int pair_fwd_min_waves() { return N <= 10 ? 2 : 1; }
 
