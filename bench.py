@@ -887,14 +887,16 @@ def adjoint_measurement(torch, ops, workloads, dev):
                                         TT["w"], dd["dt"])], 10, 3)
     # FMAs per cell of the two as implemented, at the cells' own (m*, s*):
     # forward = structured Horner (2N^2 + N per degree), Y-form squarings
-    # (N^3 each), apply (D N^2); fused = Horner on Y and dY with the rank-D
-    # direction (4N^2 + 2N + 2D N^2 per degree), three products per squaring
+    # (N^3 each), apply (D N^2); fused (the two-lane kernel at N = 8) =
+    # Horner on Y and dY with the direction as D outer products and the
+    # vectors (Y + cI) ubar_d by their own O(N) recurrence
+    # (4N^2 + 2N + D N^2 + 3 D N per degree), three products per squaring
     # (3 N^3), both applies (2 D N^2)
     _, _, _, _, mm, ss = ops.build(TT["rho_g"], TT["rho_d"], TT["t_stop"], dd["dt"])
     m, s = float(mm.double().mean()), float(ss.double().mean())
     N, D = int(TT["rho_d"].shape[0]), int(TT["v"].shape[0])
     fma_f = (2 * N * N + N) * m + N ** 3 * s + D * N * N
-    fma_b = (4 * N * N + 2 * N + 2 * D * N * N) * m + 3 * N ** 3 * s + 2 * D * N * N
+    fma_b = (4 * N * N + 2 * N + D * N * N + 3 * D * N) * m + 3 * N ** 3 * s + 2 * D * N * N
     return {"workload": "n8_adjoint_3d", "n_cells": int(dd["rho_g"].shape[0]),
             "fwd_ms": tf, "fwd_bwd_ms": tb, "fwd_bwd_over_fwd": tb / tf,
             "fma_per_cell": {"fwd": fma_f, "fwd_bwd": fma_b, "ratio": fma_b / fma_f,
