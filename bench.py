@@ -196,7 +196,7 @@ def main():
                          "takes them from a child process started this way")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(the drag update is cell-local and would shard by cell ranges)", file=sys.stderr)
         sys.exit(2)
 
