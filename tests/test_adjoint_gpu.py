@@ -97,6 +97,16 @@ def test_backward_every_n_both_mappings(ops, dev, orc, N):
         _lib.set_mapping(N, _lib.MAP_AUTO)
 
 
+@pytest.mark.parametrize("N", [7, 8, 9, 10])
+@pytest.mark.parametrize("D", [1, 2])
+def test_backward_fewer_components(ops, dev, orc, N, D):
+    """D = 1, 2 through the vector-ALU adjoints (the two-lane kernel at N = 8
+    carries one direction vector per component): against the oracle."""
+    d = _weights(W.make_stiff(N, 257, D=D), seed=10 * N + D)
+    got = gpu_backward(ops, d, dev)
+    check_vs_oracle(orc, d, got, GRAD_TOL, f"N={N} D={D}")
+
+
 def test_fused_forward_matches_forward(ops, dev):
     for name in ("n8_adjoint_3d", "n16_stiff_3d", "n4_3d"):
         d = _weights(W.make(name, 1000))
