@@ -35,13 +35,23 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _require(t, name):
+_current_device = getattr(torch._C, "_cuda_getDevice", None) or torch.cuda.current_device
+
+
+def _require(t, name, dev=None):
+    """A float64 tensor on the current GPU (the library launches on the
+    current device and takes raw pointers: memory of another device would be
+    read across the fabric, or fault)."""
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if t.dtype is not torch.float64:
         raise TypeError(f"{name} must be float64 (got {t.dtype}); there is no implicit cast")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor")
+    cur = _current_device() if dev is None else dev
+    if t.get_device() != cur:
+        raise ValueError(f"{name} is on cuda:{t.get_device()} but the current device is "
+                         f"cuda:{cur} (use torch.cuda.device(...))")
 
 
 def _ld_of(t, rows_dims, name):
@@ -70,8 +80,9 @@ def _ld_of(t, rows_dims, name):
 
 
 def _shapes(rho_g, rho_d, t_stop, v):
+    dev = _current_device()
     for x, n in ((rho_g, "rho_g"), (rho_d, "rho_d"), (t_stop, "t_stop"), (v, "v")):
-        _require(x, n)
+        _require(x, n, dev)
     sg, sd, st, sv = rho_g.shape, rho_d.shape, t_stop.shape, v.shape
     if len(sg) != 1 or len(sd) != 2 or len(st) != 2 or len(sv) != 3:
         raise ValueError("expected rho_g [C], rho_d [N][C], t_stop [N][C], v [D][N+1][C]")

@@ -1,6 +1,7 @@
-"""Host-side checks of the Python binding (no GPU needed): outputs it
-allocates share the caller's leading dimension, since the library addresses
-every [.][ld] array with the one ld of the descriptor."""
+"""Host-side checks of the Python binding: outputs it allocates share the
+caller's leading dimension, since the library addresses every [.][ld] array
+with the one ld of the descriptor; and (on a GPU) tensors off the current
+device are refused."""
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -45,7 +46,8 @@ def test_shapes_share_one_leading_dimension(monkeypatch):
     """_shapes on host tensors (the device check switched off): a padded v
     sets ld even at N = 1, D = 1; mismatched row strides are refused."""
     from paper_2509_25347_amd import ops
-    monkeypatch.setattr(ops, "_require", lambda t, name: None)
+    monkeypatch.setattr(ops, "_require", lambda t, name, dev=None: None)
+    monkeypatch.setattr(ops, "_current_device", lambda: 0)
     C, ld = 100, 128
     rho_g = torch.zeros(C, dtype=torch.float64)
     rho_d = torch.zeros((1, 1000), dtype=torch.float64)[:, :C]  # one row: no constraint
@@ -65,7 +67,8 @@ def test_overlapping_rows_are_refused(monkeypatch):
     """An expand()ed view (row stride 0) or rows closer than the cell count
     share storage; the library would read D (N+1) ld doubles from it."""
     from paper_2509_25347_amd import ops
-    monkeypatch.setattr(ops, "_require", lambda t, name: None)
+    monkeypatch.setattr(ops, "_require", lambda t, name, dev=None: None)
+    monkeypatch.setattr(ops, "_current_device", lambda: 0)
     v = torch.zeros(100, dtype=torch.float64).view(1, 1, 100).expand(3, 2, 100)
     with pytest.raises(ValueError):
         ops._ld_of(v, 2, "v")
@@ -109,3 +112,21 @@ def test_autograd_backward_hands_contiguous_inputs(monkeypatch):
     grads = ops.DragExpm.backward(Ctx(), torch.zeros((D, N + 1, ld), dtype=torch.float64)[..., :C])
     assert seen["contiguous"]
     assert grads[3].shape == (D, N + 1, C)
+
+
+@pytest.mark.gpu
+def test_tensors_off_the_current_device_are_refused(monkeypatch):
+    """The library launches on the current device with raw pointers: a tensor
+    of another device is refused before anything is enqueued (simulated on
+    one GPU by moving the current device)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_25347_amd import ops, workloads
+    d = workloads.make("n4_3d", 64)
+    T = {k: torch.from_numpy(d[k]).cuda() for k in ("rho_g", "rho_d", "t_stop", "v")}
+    ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"])
+    monkeypatch.setattr(ops, "_current_device", lambda: T["v"].get_device() + 1)
+    with pytest.raises(ValueError, match="current device"):
+        ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"])
+    with pytest.raises(ValueError, match="current device"):
+        ops.rk1_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"])
