@@ -29,8 +29,11 @@
  * return DRAG_ERR_N_SPECIES above 16.
  *
  * Ownership and synchronisation: every array pointer is a device pointer
- * owned by the caller.  drag_build, drag_expm_apply, drag_expm_apply_backward
- * and drag_clear_status only enqueue work on `stream` (a hipStream_t; NULL is
+ * owned by the caller, in memory of the current device (hipSetDevice), where
+ * the kernels run; `stream` must belong to that device too (neither is
+ * checked: a pointer of another device is read across the fabric or faults).
+ * drag_build, drag_expm_apply, drag_expm_apply_backward and
+ * drag_clear_status only enqueue work on `stream` (a hipStream_t; NULL is
  * the null stream): they never allocate device memory, never synchronise, and
  * return before the work is done.  drag_get_status and drag_plan_autotune
  * synchronise `stream`; the batched plan calls allocate and free the plan's
