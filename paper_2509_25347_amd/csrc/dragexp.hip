@@ -361,9 +361,10 @@ static int mapping_for_bwd(int N) {
 // MFMA kernel is flat for K >= 7.  The table holds, per N, the K with the
 // least summed time over the stiff and the jittered recipes (2^18 cells,
 // `bench.py --k-sweep`: every K = 2..9, interleaved repeats): against K = 9
-// it takes 0.86-0.94 of the time for N = 2..8, 0.92-0.94 on the
-// two-lanes-per-cell kernel (N = 9..12), 0.99-1.0 on the MFMA kernel; for
-// N = 1..3 a neighbouring K is within 0.1-1.6 % (noise at these times).
+// it takes 0.84-0.96 of the time for N = 2..8, 0.92-0.95 on the
+// two-lanes-per-cell kernel (N = 9..12), 0.99 on the MFMA kernel; at
+// N = 1, 2, 8, 10 another K is faster by 0.4-1.3 %, about the spread of
+// repeated runs.
 static const int g_default_kmax[16] = {4, 3, 4, 5, 5, 6, 5, 6, 6, 6, 6, 6, 7, 7, 7, 7};
 static int g_kmax_override[16] = {0};
 
