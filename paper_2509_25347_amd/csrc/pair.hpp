@@ -357,7 +357,9 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
     // v and w of this cell: at N <= 8 rebuilt from LDS (v_k = v_0 + dv_k,
     // w_k = ubar_k + W e_k / sigma, each within a rounding of the input) rather
     // than read again from memory after the squarings; at N = 9, 10 the
-    // rebuild's registers would spill, so those read them again
+    // rebuild's registers would spill, so those read them again, and so does
+    // dt = 0 (Z = 0: v' = v and dL/dv = w bit for bit)
+    const bool reread = !kRebuild || A.dt == 0.0;  // uniform
     const double W = my[(kGas + 6 + d) * kStride];
     const int64_t base = (int64_t)(d * n1) * ld + c;
 #pragma unroll
@@ -371,8 +373,14 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
         if (k < N) {
           const int64_t idx = base + (int64_t)(1 + k) * ld;
           const double e_k = my[(7 * W2 + k) * kStride];
-          const double vk = kRebuild ? v0 + dv[r] : A.v_in[idx];
-          const double wk = kRebuild ? ub[r] + W * e_k / sigma : A.w[idx];
+          double vk, wk;
+          if (reread) {
+            vk = A.v_in[idx];
+            wk = A.w[idx];
+          } else {
+            vk = v0 + dv[r];
+            wk = ub[r] + W * e_k / sigma;
+          }
           if (A.v_out) A.v_out[idx] = bad ? qnan : vk + (d0 + u[r]);
           if (A.g_v) A.g_v[idx] = bad ? qnan : wk + zt[r];
         }
