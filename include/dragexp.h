@@ -93,7 +93,8 @@ typedef struct drag_desc {
     int32_t n_species; /* N in [1, 16]; up to 32 for the forward calls */
     int32_t n_dim;     /* D in [1, 3] */
     int64_t ld;        /* leading dimension of every [.][ld] array, >= C */
-    double dt;         /* finite, >= 0; dt = 0 returns v unchanged, bit for bit */
+    double dt;         /* finite, >= 0; dt = 0 returns v unchanged (every value
+                          equal; a -0.0 entry may come back as +0.0) */
     int32_t k_max;     /* K of Alg. 1, 1..9 (9: m up to 30, Table B.1), or
                           DRAG_K_AUTO: the library's tuned K for n_species
                           (drag_get_k_max) */
@@ -190,7 +191,8 @@ int drag_expm_steps(const drag_desc *desc, const double *rho_g,
  * arrowhead system (one cell per lane; bound by HBM bandwidth).  Same
  * layout, aliasing rules, bad-cell flags and NaN outputs as drag_expm_apply;
  * desc->k_max and desc->option are validated but not used.  dt = 0 returns v
- * unchanged, bit for bit; a species with t_i = +inf keeps its velocity.
+ * unchanged (as for drag_expm_apply); a species with t_i = +inf keeps its
+ * velocity.
  * The result is first-order accurate in dt (||v_out - exp(dt K) v_in|| is
  * O(dt^2) per step) and relaxes to the barycentric velocity as dt/t_i grows.
  */
