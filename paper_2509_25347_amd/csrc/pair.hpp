@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(256, kMinWaves) k_backward_pair(BackArgs A, in
     // w_k = ubar_k + W e_k / sigma, each within a rounding of the input) rather
     // than read again from memory after the squarings; at N = 9, 10 the
     // rebuild's registers would spill, so those read them again, and so does
-    // dt = 0 (Z = 0: v' = v and dL/dv = w bit for bit)
+    // dt = 0 (Z = 0: v' and dL/dv equal v and w)
     const bool reread = !kRebuild || A.dt == 0.0;  // uniform
     const double W = my[(kGas + 6 + d) * kStride];
     const int64_t base = (int64_t)(d * n1) * ld + c;
