@@ -934,7 +934,7 @@ int drag_expm_steps(const drag_desc* d, const double* rho_g, const double* rho_d
       if (!v_in || !v_out) return DRAG_ERR_NULL_POINTER;
       // zero steps: v_out = v_in
       drag_desc one = *d;
-      one.dt = 0.0;  // the exact identity, bit for bit
+      one.dt = 0.0;  // the identity (equal values)
       return drag_expm_apply(&one, rho_g, rho_d, t_stop, v_in, v_out, stream);
     }
     return DRAG_OK;
