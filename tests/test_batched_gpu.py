@@ -102,6 +102,25 @@ def test_autotune_and_every_variant_result(ops, dev):
     plan.close()
 
 
+def test_dt_zero_returns_the_input(ops, dev):
+    """dt = 0 through every form of the batched update (each lane bound's grids
+    and the four MFMA forms, and the entry point without allocation): exp(0) = I,
+    so every block comes back with its input values."""
+    batch = W.make_batched(n_blocks=48, block_cells=64, seed_cfg=47)
+    plan = ops.BatchPlan(batch["n_species"], 64, 3, 0.0)
+    fields, v = plan.pack(batch["blocks"], dev)
+    for lmax in (4, 8, 12):
+        for mode in ("persistent", "grid", "per_n", "per_n_pade"):
+            plan.set_config(lmax, mode)
+            out = plan.apply(fields, v)
+            torch.cuda.synchronize()
+            assert torch.equal(out, v), (lmax, mode)
+    plan.close()
+    out = ops.expm_apply_batched_static(batch["n_species"], 64, 3, 0.0, fields, v)
+    torch.cuda.synchronize()
+    assert torch.equal(out, v)
+
+
 def test_pade_per_n_form_against_the_oracle(ops, dev, orc):
     """The per_n_pade form: blocks above the lane bound against the oracle's
     Pade step (its dense (N+1) form) and the exact exponential, to the
