@@ -186,3 +186,29 @@ def test_stream_sizes_at_the_pass_boundaries(ops, dev, orc, N, cells):
     print(f"stream sizes N={N} cells={cells}", flush=True)
     got = run(ops, d, dev)
     check_forward(orc, got, ref, d, f"N={N} cells={cells}")
+
+
+@pytest.mark.parametrize("N", [4, 8])
+def test_arrays_past_32_bit_offsets(ops, dev, N):
+    """Arrays whose byte span passes 2^32 (here by a large leading dimension)
+    leave the one-lane kernels' 32-bit buffer offsets for the 64-bit
+    addressed one-shot kernel: the same cells give the same bits as in a
+    compact layout (about 20 GB of device memory, only the first cells of
+    each row written)."""
+    d = _make(N, 1000, 1)
+    C = 1000
+    ld = (1 << 32) // (8 * N) + 64  # 8 (N ld + C) > 2^32 for the velocity rows
+    print(f"32-bit offsets N={N} ld={ld}", flush=True)
+    T = {k: torch.from_numpy(np.ascontiguousarray(d[k])).to(dev)
+         for k in ("rho_g", "rho_d", "t_stop", "v")}
+    ref = ops.expm_apply(T["rho_g"], T["rho_d"], T["t_stop"], T["v"], d["dt"])
+    big = {}
+    for k in ("rho_d", "t_stop", "v"):
+        full = torch.empty(tuple(T[k].shape[:-1]) + (ld,), dtype=torch.float64, device=dev)
+        full[..., :C] = T[k]
+        big[k] = full[..., :C]
+    out = ops.expm_apply(T["rho_g"], big["rho_d"], big["t_stop"], big["v"], d["dt"])
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    del big, out
+    torch.cuda.empty_cache()
